@@ -1,0 +1,159 @@
+/*
+ * sp2.h -- C ABI of libsp2: SP2 density matrices on AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates the zero-temperature density matrix D = theta(mu I - H)
+ * (Eq. 3) of a dense symmetric Hamiltonian H by the Deep-NN formulation of the
+ * second-order spectral projection recursion (Alg. 1): a rescale of H into [0,1]
+ * with reversed order, a chain of matrix squarings S <- S^2 or 2S - S^2 chosen by
+ * trace, the parameter-free stopping test of Alg. 1, and the enhanced-precision
+ * refinement layer of Eq. Refinement.  The squarings can run in FP64, FP32 or in
+ * the dual half-precision form of Alg. 2 (Eqs. Split1, Split2, Square) with FP32
+ * accumulation; traces, bounds and the final checks are always FP64.
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are row-major with a leading dimension (ld >= n, in elements).  For a
+ *     symmetric matrix row- and column-major coincide.
+ *   - Every matrix and workspace pointer is a DEVICE pointer owned by the caller.
+ *     The library never allocates or frees device memory and keeps no state between
+ *     calls; all per-call state lives in the caller's workspace.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  All
+ *     work is enqueued on it.  A call with `info == NULL` returns after enqueueing,
+ *     without synchronizing; device-side outcomes can be read later with sp2_query.
+ *     A call with `info != NULL` synchronizes the stream and fills *info.
+ *   - Errors: argument errors are detected on the host before anything is enqueued
+ *     and return SP2_EINVAL.  HIP errors return SP2_EDEVICE.  Numerical outcomes
+ *     (non-finite values, no convergence, result not idempotent) are detected on the
+ *     device and returned when the call synchronizes; D is written in every one of
+ *     these numerical cases.
+ */
+#ifndef SP2_H
+#define SP2_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SP2_OK = 0,
+    SP2_EINVAL = -1,      /* bad argument, or H not symmetric (checked on the device) */
+    SP2_ENONFINITE = -2,  /* NaN/Inf in H or in a layer */
+    SP2_ENOCONV = -3,     /* max_layers reached before a stopping test of Alg. 1 held */
+    SP2_ENOTIDEMP = -4,   /* |Tr D - n_occ| or |Tr[D - D^2]| above tolerance */
+    SP2_EDEVICE = -5,     /* a HIP call failed */
+    SP2_ENOMEM = -6       /* workspace smaller than sp2_workspace_size() */
+} sp2_status;
+
+/* Arithmetic of the squaring layers (the activation f(X) = X^2 of Alg. 1). */
+typedef enum {
+    SP2_FP64 = 0,    /* FP64 matrix cores, FP64 state */
+    SP2_FP32 = 1,    /* FP32 matrix cores, FP32 state */
+    SP2_FP16X2 = 2,  /* Alg. 2: X = X0 + X1 in two FP16 planes, 3 products, FP32 accumulate */
+    SP2_BF16X2 = 3   /* the same with BF16 planes */
+} sp2_precision;
+
+#define SP2_MAX_LAYERS 128   /* capacity of the per-layer history; max_layers <= 127 */
+
+typedef struct {
+    int precision;     /* sp2_precision; default SP2_FP16X2 */
+    int max_layers;    /* 1..127; default 100 */
+    double eps;        /* the small constant epsilon of Alg. 1 (alternation bias); default 0 */
+    int have_bounds;   /* nonzero: use [emin, emax] below as the spectral bounds of Alg. 1
+                          (they must enclose the spectrum); zero: Gershgorin bounds computed
+                          on the device in FP64 and widened outward by the rounding bound */
+    double emin, emax;
+    int refine;        /* nonzero (default): final layer f_final of Eq. Refinement in FP64;
+                          zero: D = S_{m-1} widened to FP64 */
+    int scale_log2;    /* split modes: both half-precision planes hold 2^s X (an exact shift
+                          that keeps the low plane out of the FP16 subnormal range; the
+                          products are scaled back by 2^-2s).  -1 (default) selects 12 for
+                          FP16X2 and 0 for BF16X2; 0 is the paper's split exactly. */
+    int want_energy;   /* nonzero: info->energy = Tr[D H] (the observable of Alg. 1) */
+    int tile;          /* output tile edge of the squaring kernels: 0 = automatic, or 64/128/256 */
+} sp2_options;
+
+typedef struct {
+    int status;            /* sp2_status of the device-side checks */
+    int layers;            /* m: the layer at which Alg. 1 stopped (S_{m-1} is refined) */
+    int converged;         /* 1 if a stopping test of Alg. 1 held */
+    int first_sign;        /* sign of the first of the two composed refinement steps */
+    int n_padded;          /* internal matrix edge (n rounded up to the tile) */
+    int tile;              /* output tile edge used */
+    double emin, emax;     /* spectral bounds used */
+    double trace;          /* Tr D */
+    double idem;           /* Tr D - ||D||_F^2  (= Tr[D - D^2] for symmetric D) */
+    double energy;         /* Tr[D H] if requested, else 0 */
+    double asym;           /* max |H_ij - H_ji| */
+    signed char sigma[SP2_MAX_LAYERS];  /* sigma_n, n = 1..layers at index n-1 */
+    double iderr[SP2_MAX_LAYERS];       /* IdErr_n = Tr[S_{n-1} - S_{n-1}^2] */
+    double ns[SP2_MAX_LAYERS];          /* N_S entering layer n: Tr S_{n-1} */
+    double nx[SP2_MAX_LAYERS];          /* N_X of layer n: Tr X_n = ||S_{n-1}||_F^2 */
+} sp2_info;
+
+/* Fill *opt with the defaults listed above. */
+void sp2_default_options(sp2_options* opt);
+
+/* Short description of a status code (static storage). */
+const char* sp2_strerror(int status);
+
+/* Library version string (static storage). */
+const char* sp2_version(void);
+
+/*
+ * Workspace bytes needed by sp2_density for an n x n problem with these options
+ * (opt may be NULL for defaults).  Returns 0 for n <= 0.
+ */
+size_t sp2_workspace_size(int n, const sp2_options* opt);
+
+/*
+ * sp2_density -- D = theta(mu I - H) with Tr D = n_occ, by Alg. 1.
+ *
+ *   dH     device, n x n FP64, leading dimension ldh >= n, symmetric; read only.
+ *          Non-symmetric input (max|H_ij - H_ji| > 1e-12 * max(|emin|,|emax|,1)) is
+ *          reported as SP2_EINVAL by the device check; the layers use (H + H^T)/2.
+ *   dD     device, n x n FP64 output, leading dimension ldd >= n; exactly symmetric.
+ *   n      matrix edge, >= 1.
+ *   n_occ  number of occupied states, 0 <= n_occ <= n.  0 and n return D = 0 and
+ *          D = I without running the recursion.
+ *   tol    acceptance threshold: D is accepted when |Tr D - n_occ| <= tol and
+ *          |Tr[D - D^2]| <= tol; tol <= 0 selects 1e-6 and 1e-6 * n.  The stopping
+ *          rule of the recursion itself is Alg. 1's parameter-free test.
+ *   opt    options (NULL = defaults).
+ *   info   host pointer or NULL; see the stream conventions above.
+ *   dWork  device workspace of work_bytes >= sp2_workspace_size(n, opt) bytes,
+ *          256-byte aligned.  Its contents after the call describe the run (sp2_query).
+ *   stream hipStream_t or NULL.
+ */
+int sp2_density(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ, double tol,
+                const sp2_options* opt, sp2_info* info, void* dWork, size_t work_bytes,
+                void* stream);
+
+/*
+ * sp2_query -- synchronize `stream` and read the outcome of the last sp2_density call
+ * that used this workspace (with the same n and options) into *info.  Returns the
+ * device-side status.
+ */
+int sp2_query(const void* dWork, int n, const sp2_options* opt, sp2_info* info, void* stream);
+
+/*
+ * sp2_square -- one activation layer of Alg. 1 as a standalone operation (for tests
+ * and benchmarks): Y = alpha X^2 + beta X + gamma I for a symmetric n x n matrix X
+ * given in the state precision of `precision` (FP64 for SP2_FP64, FP32 otherwise;
+ * leading dimension ld = n_padded from sp2_square_padded), written to dY with the same
+ * layout.  For the split modes the planes of X are formed internally (Eq. Split2) and
+ * the square uses Eq. Square.  The output is exactly symmetric.  dWork must hold
+ * sp2_square_workspace_size(n, precision, tile) bytes.  Also returns, if trace_frob is
+ * non-NULL (host, 2 doubles), Tr Y and ||Y||_F^2 in FP64 (synchronizes).
+ */
+int sp2_square_padded(int n, int precision, int tile);
+size_t sp2_square_workspace_size(int n, int precision, int tile);
+int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int scale_log2,
+               float alpha, float beta, float gamma, double* trace_frob, void* dWork,
+               size_t work_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SP2_H */

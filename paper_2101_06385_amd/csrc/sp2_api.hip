@@ -1,0 +1,393 @@
+// Host side of libsp2: argument checks, workspace layout and the launch sequence of
+// Alg. 1.  Control stays on the device: every layer is a control kernel (IdErr_n,
+// sigma_n, stopping tests) followed by a squaring kernel that reads its coefficients
+// and a skip flag from the device state, so the host enqueues the whole recursion
+// without reading anything back.
+#include "sp2_internal.h"
+
+#include <math.h>
+#include <string.h>
+
+using namespace sp2;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+struct Opts {
+    int precision, max_layers, have_bounds, refine, scale_log2, want_energy, tile;
+    double eps, emin, emax;
+};
+
+bool read_opts(const sp2_options* o, Opts* r) {
+    sp2_options d;
+    sp2_default_options(&d);
+    if (!o) o = &d;
+    r->precision = o->precision;
+    r->max_layers = o->max_layers == 0 ? 100 : o->max_layers;
+    r->have_bounds = o->have_bounds;
+    r->refine = o->refine;
+    r->want_energy = o->want_energy;
+    r->tile = o->tile;
+    r->eps = o->eps;
+    r->emin = o->emin;
+    r->emax = o->emax;
+    if (r->precision < SP2_FP64 || r->precision > SP2_BF16X2) return false;
+    const bool split = r->precision == SP2_FP16X2 || r->precision == SP2_BF16X2;
+    r->scale_log2 = o->scale_log2 < 0 ? (r->precision == SP2_FP16X2 ? 12 : 0) : o->scale_log2;
+    if (!split) r->scale_log2 = 0;
+    if (r->scale_log2 > (r->precision == SP2_FP16X2 ? 14 : 60)) return false;
+    if (r->max_layers < 1 || r->max_layers >= SP2_MAX_LAYERS) return false;
+    if (r->tile != 0 && r->tile != 64 && r->tile != 128 && r->tile != 256) return false;
+    if (r->tile == 256 && !split) return false;
+    if (!isfinite(r->eps)) return false;
+    if (r->have_bounds && !(isfinite(r->emin) && isfinite(r->emax) && r->emax > r->emin)) return false;
+    return true;
+}
+
+struct Plan {
+    int n, np, precision, tile_main, tile_ref, scale_log2;
+    bool split;
+    int init_tiles, main_T, main_tiles, main_per, ref_T, ref_tiles, ref_per, gersh_blocks, dstats_blocks;
+    size_t off_init_parts, off_main_parts, off_gersh, off_dstats, off_s[2], off_p[2][2], off_s64, off_y, total;
+};
+
+int auto_tile_main(int n, bool split) {
+    if (split) return n <= 256 ? 64 : (n <= 2048 ? 128 : 256);
+    return n <= 512 ? 64 : 128;
+}
+
+void make_plan(int n, const Opts& o, Plan* p) {
+    p->n = n;
+    p->precision = o.precision;
+    p->split = o.precision == SP2_FP16X2 || o.precision == SP2_BF16X2;
+    p->scale_log2 = o.scale_log2;
+    p->tile_main = o.tile ? o.tile : auto_tile_main(n, p->split);
+    p->tile_ref = n <= 512 ? 64 : 128;
+    const int m = p->tile_main > p->tile_ref ? p->tile_main : p->tile_ref;
+    p->np = round_up(n, m);
+    p->init_tiles = init_tiles(p->np);
+    if (p->split)
+        square_split_grid(p->tile_main, p->np, &p->main_T, &p->main_tiles, &p->main_per);
+    else
+        square_plain_grid(p->tile_main, p->np, &p->main_T, &p->main_tiles, &p->main_per);
+    square_plain_grid(p->tile_ref, p->np, &p->ref_T, &p->ref_tiles, &p->ref_per);
+    p->gersh_blocks = gershgorin_blocks(n);
+    p->dstats_blocks = dstats_blocks(n);
+    const size_t np2 = (size_t)p->np * p->np;
+    const size_t es = o.precision == SP2_FP64 ? 8 : 4;
+    size_t off = align_up(sizeof(DevState));
+    p->off_init_parts = off;
+    off = align_up(off + sizeof(double) * 3 * p->init_tiles);
+    p->off_main_parts = off;
+    off = align_up(off + sizeof(double) * 2 * p->main_tiles);
+    p->off_gersh = off;
+    off = align_up(off + sizeof(double) * 3 * p->gersh_blocks);
+    p->off_dstats = off;
+    off = align_up(off + sizeof(double) * 3 * p->dstats_blocks);
+    for (int i = 0; i < 2; ++i) {
+        p->off_s[i] = off;
+        off = align_up(off + es * np2);
+    }
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            p->off_p[i][j] = off;
+            if (p->split) off = align_up(off + 2 * np2);
+        }
+    p->off_s64 = off;
+    off = align_up(off + (o.refine ? 8 * np2 : 0));
+    p->off_y = off;
+    off = align_up(off + (o.refine ? 8 * np2 : 0));
+    p->total = off;
+}
+
+void fill_info(const DevState& st, const Plan* p, sp2_info* info) {
+    memset(info, 0, sizeof(*info));
+    info->status = st.status;
+    info->layers = st.layers;
+    info->converged = st.converged;
+    info->first_sign = st.first_sign;
+    info->n_padded = st.n_padded;
+    info->tile = st.tile;
+    info->emin = st.emin;
+    info->emax = st.emax;
+    info->trace = st.trace_d;
+    info->idem = st.trace_d - st.frob_d;
+    info->energy = st.energy;
+    info->asym = st.asym;
+    for (int k = 1; k <= SP2_MAX_LAYERS; ++k) {
+        info->sigma[k - 1] = st.sigma[k];
+        info->iderr[k - 1] = st.iderr[k];
+        info->ns[k - 1] = st.ns[k];
+        info->nx[k - 1] = st.nx[k];
+    }
+    (void)p;
+}
+
+#define SP2_TRY(expr)                                   \
+    do {                                                \
+        if ((expr) != hipSuccess) return SP2_EDEVICE;   \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+void sp2_default_options(sp2_options* opt) {
+    if (!opt) return;
+    memset(opt, 0, sizeof(*opt));
+    opt->precision = SP2_FP16X2;
+    opt->max_layers = 100;
+    opt->eps = 0.0;
+    opt->have_bounds = 0;
+    opt->emin = 0.0;
+    opt->emax = 0.0;
+    opt->refine = 1;
+    opt->scale_log2 = -1;
+    opt->want_energy = 0;
+    opt->tile = 0;
+}
+
+const char* sp2_strerror(int status) {
+    switch (status) {
+        case SP2_OK: return "success";
+        case SP2_EINVAL: return "invalid argument or non-symmetric H";
+        case SP2_ENONFINITE: return "non-finite value in H or in a layer";
+        case SP2_ENOCONV: return "max_layers reached before the stopping test held";
+        case SP2_ENOTIDEMP: return "result not idempotent or wrong occupation";
+        case SP2_EDEVICE: return "HIP runtime error";
+        case SP2_ENOMEM: return "workspace too small";
+        default: return "unknown status";
+    }
+}
+
+const char* sp2_version(void) { return "libsp2 0.1 (gfx950)"; }
+
+size_t sp2_workspace_size(int n, const sp2_options* opt) {
+    if (n <= 0) return 0;
+    Opts o;
+    if (!read_opts(opt, &o)) return 0;
+    Plan p;
+    make_plan(n, o, &p);
+    return p.total;
+}
+
+int sp2_density(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ, double tol,
+                const sp2_options* opt, sp2_info* info, void* dWork, size_t work_bytes, void* stream) {
+    Opts o;
+    if (!read_opts(opt, &o)) return SP2_EINVAL;
+    if (n <= 0 || ldh < n || ldd < n || n_occ < 0 || n_occ > n || !dH || !dD || !dWork) return SP2_EINVAL;
+    if (((uintptr_t)dWork) % kAlign) return SP2_EINVAL;
+    if (n > 65536) return SP2_EINVAL;
+    Plan p;
+    make_plan(n, o, &p);
+    if (work_bytes < p.total) return SP2_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)dWork;
+    DevState* st = (DevState*)ws;
+
+    DevState init;
+    memset(&init, 0, sizeof(init));
+    init.n = n;
+    init.n_occ = n_occ;
+    init.n_padded = p.np;
+    init.max_layers = o.max_layers;
+    init.precision = o.precision;
+    init.tile = p.tile_main;
+    init.have_bounds = o.have_bounds;
+    init.want_energy = o.want_energy;
+    init.eps = o.eps;
+    init.tol_tr = tol > 0 ? tol : 1e-6;
+    init.tol_id = tol > 0 ? tol : 1e-6 * n;
+    init.emin = o.have_bounds ? o.emin : 0.0;
+    init.emax = o.have_bounds ? o.emax : 1.0;
+    SP2_TRY(launch_state_init(st, init, s));
+
+    double* init_parts = (double*)(ws + p.off_init_parts);
+    double* main_parts = (double*)(ws + p.off_main_parts);
+    double* dstats = (double*)(ws + p.off_dstats);
+
+    if (n_occ == 0 || n_occ == n) {
+        // D = 0 or I: the projector is fixed by the occupation alone
+        SP2_TRY(launch_fill(dD, ldd, n, n_occ == n ? 1.0 : 0.0, s));
+        int nd = 0;
+        SP2_TRY(launch_dstats(dD, ldd, o.want_energy ? dH : nullptr, ldh, n, dstats, &nd, s));
+        SP2_TRY(launch_mark_trivial(st, s));
+        SP2_TRY(launch_finalize(st, dstats, nd, init_parts, 0, s));
+    } else {
+        if (!o.have_bounds) {
+            int nb = 0;
+            double* gersh = (double*)(ws + p.off_gersh);
+            SP2_TRY(launch_gershgorin(dH, ldh, n, gersh, &nb, s));
+            SP2_TRY(launch_bounds(st, gersh, nb, s));
+        }
+        void* S[2] = {ws + p.off_s[0], ws + p.off_s[1]};
+        void* P[2][2] = {{p.split ? ws + p.off_p[0][0] : nullptr, p.split ? ws + p.off_p[0][1] : nullptr},
+                         {p.split ? ws + p.off_p[1][0] : nullptr, p.split ? ws + p.off_p[1][1] : nullptr}};
+        SP2_TRY(launch_init_np(dH, ldh, st, p.np, o.precision, S[0], P[0][0], P[0][1], p.scale_log2, init_parts, s));
+
+        SquareArgs a;
+        memset(&a, 0, sizeof(a));
+        a.parts = main_parts;
+        a.coef = st->coef;
+        a.skip = &st->skip;
+        a.np = p.np;
+        a.ld_out = p.np;
+        a.n_valid = p.np;
+        a.T = p.main_T;
+        a.ntiles = p.main_tiles;
+        a.per = p.main_per;
+        a.out_scale = ldexpf(1.f, -2 * p.scale_log2);
+        a.in_scale = ldexpf(1.f, p.scale_log2);
+        for (int layer = 1; layer <= o.max_layers + 1; ++layer) {
+            if (layer == 1)
+                SP2_TRY(launch_control_stride(st, init_parts, p.init_tiles, 3, layer, s));
+            else
+                SP2_TRY(launch_control_stride(st, main_parts, p.main_tiles, 2, layer, s));
+            if (layer > o.max_layers) break;
+            const int in = (layer - 1) & 1, out = layer & 1;
+            a.x0 = p.split ? P[in][0] : S[in];
+            a.x1 = p.split ? P[in][1] : nullptr;
+            a.s_in = S[in];
+            a.s_out = S[out];
+            a.p0_out = P[out][0];
+            a.p1_out = P[out][1];
+            if (p.split)
+                SP2_TRY(launch_square_split(o.precision, p.tile_main, a, s));
+            else
+                SP2_TRY(launch_square_plain(o.precision, p.tile_main, a, s));
+        }
+        if (o.refine) {
+            double* s64 = (double*)(ws + p.off_s64);
+            double* y = (double*)(ws + p.off_y);
+            SP2_TRY(launch_select_f64(st, S[0], S[1], o.precision == SP2_FP64, s64, p.np, p.np, p.np, s));
+            SquareArgs r;
+            memset(&r, 0, sizeof(r));
+            r.np = p.np;
+            r.T = p.ref_T;
+            r.ntiles = p.ref_tiles;
+            r.per = p.ref_per;
+            r.x0 = s64;
+            r.s_in = s64;
+            r.s_out = y;
+            r.ld_out = p.np;
+            r.n_valid = p.np;
+            r.coef = st->rcoef[0];
+            SP2_TRY(launch_square_plain(SP2_FP64, p.tile_ref, r, s));
+            r.x0 = y;
+            r.s_in = y;
+            r.s_out = dD;
+            r.ld_out = ldd;
+            r.n_valid = n;
+            r.coef = st->rcoef[1];
+            SP2_TRY(launch_square_plain(SP2_FP64, p.tile_ref, r, s));
+        } else {
+            SP2_TRY(launch_select_f64(st, S[0], S[1], o.precision == SP2_FP64, dD, ldd, n, p.np, s));
+        }
+        int nd = 0;
+        SP2_TRY(launch_dstats(dD, ldd, o.want_energy ? dH : nullptr, ldh, n, dstats, &nd, s));
+        SP2_TRY(launch_finalize(st, dstats, nd, init_parts, p.init_tiles, s));
+    }
+    if (!info) return SP2_OK;
+    DevState host;
+    SP2_TRY(hipStreamSynchronize(s));
+    SP2_TRY(hipMemcpy(&host, st, sizeof(DevState), hipMemcpyDeviceToHost));
+    fill_info(host, &p, info);
+    return host.status;
+}
+
+int sp2_query(const void* dWork, int n, const sp2_options* opt, sp2_info* info, void* stream) {
+    Opts o;
+    if (!dWork || !info || n <= 0 || !read_opts(opt, &o)) return SP2_EINVAL;
+    Plan p;
+    make_plan(n, o, &p);
+    DevState host;
+    SP2_TRY(hipStreamSynchronize((hipStream_t)stream));
+    SP2_TRY(hipMemcpy(&host, dWork, sizeof(DevState), hipMemcpyDeviceToHost));
+    fill_info(host, &p, info);
+    return host.status;
+}
+
+int sp2_square_padded(int n, int precision, int tile) {
+    if (n <= 0) return 0;
+    const bool split = precision == SP2_FP16X2 || precision == SP2_BF16X2;
+    const int t = tile ? tile : auto_tile_main(n, split);
+    return round_up(n, t);
+}
+
+size_t sp2_square_workspace_size(int n, int precision, int tile) {
+    const int np = sp2_square_padded(n, precision, tile);
+    if (np <= 0) return 0;
+    const bool split = precision == SP2_FP16X2 || precision == SP2_BF16X2;
+    const int t = tile ? tile : auto_tile_main(n, split);
+    int T, nt, per;
+    if (split) square_split_grid(t, np, &T, &nt, &per);
+    else square_plain_grid(t, np, &T, &nt, &per);
+    size_t off = kAlign;                               // coefficients
+    off = align_up(off + sizeof(double) * 2 * nt);     // partials
+    off = align_up(off + sizeof(double) * 2);          // sums
+    if (split) off = align_up(off + 4 * (size_t)np * np);
+    return off;
+}
+
+int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int scale_log2, float alpha, float beta,
+               float gamma, double* trace_frob, void* dWork, size_t work_bytes, void* stream) {
+    if (!dX || !dY || !dWork || n <= 0) return SP2_EINVAL;
+    if (precision < SP2_FP64 || precision > SP2_BF16X2) return SP2_EINVAL;
+    const bool split = precision == SP2_FP16X2 || precision == SP2_BF16X2;
+    if (tile != 0 && tile != 64 && tile != 128 && !(tile == 256 && split)) return SP2_EINVAL;
+    if (scale_log2 < 0) scale_log2 = precision == SP2_FP16X2 ? 12 : 0;
+    if (!split) scale_log2 = 0;
+    if (scale_log2 > (precision == SP2_FP16X2 ? 14 : 60)) return SP2_EINVAL;
+    if (((uintptr_t)dWork) % kAlign) return SP2_EINVAL;
+    const int t = tile ? tile : auto_tile_main(n, split);
+    const int np = round_up(n, t);
+    if (work_bytes < sp2_square_workspace_size(n, precision, tile)) return SP2_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)dWork;
+    int T, nt, per;
+    if (split) square_split_grid(t, np, &T, &nt, &per);
+    else square_plain_grid(t, np, &T, &nt, &per);
+    float* coef = (float*)ws;
+    double* parts = (double*)(ws + kAlign);
+    size_t off = align_up(kAlign + sizeof(double) * 2 * nt);
+    double* sums = (double*)(ws + off);
+    off = align_up(off + sizeof(double) * 2);
+    SP2_TRY(launch_set3(coef, alpha, beta, gamma, s));
+    SquareArgs a;
+    memset(&a, 0, sizeof(a));
+    a.s_in = dX;
+    a.s_out = dY;
+    a.parts = parts;
+    a.coef = coef;
+    a.np = np;
+    a.ld_out = np;
+    a.n_valid = np;
+    a.T = T;
+    a.ntiles = nt;
+    a.per = per;
+    a.out_scale = ldexpf(1.f, -2 * scale_log2);
+    a.in_scale = ldexpf(1.f, scale_log2);
+    if (split) {
+        void* p0 = ws + off;
+        void* p1 = ws + off + 2 * (size_t)np * np;
+        SP2_TRY(launch_split((const float*)dX, p0, p1, np, precision, scale_log2, s));
+        a.x0 = p0;
+        a.x1 = p1;
+        SP2_TRY(launch_square_split(precision, t, a, s));
+    } else {
+        a.x0 = dX;
+        SP2_TRY(launch_square_plain(precision, t, a, s));
+    }
+    if (trace_frob) {
+        SP2_TRY(launch_sum_parts(parts, nt, sums, s));
+        SP2_TRY(hipStreamSynchronize(s));
+        SP2_TRY(hipMemcpy(trace_frob, sums, 2 * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    return SP2_OK;
+}
+
+}  // extern "C"

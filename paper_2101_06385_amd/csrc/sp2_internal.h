@@ -1,0 +1,136 @@
+// Internal declarations shared by the HIP kernels and the host driver of libsp2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/sp2.h"
+
+namespace sp2 {
+
+// ---------------------------------------------------------------------------------
+// Per-call device state: lives at the start of the caller's workspace.
+// Written by the control kernels; read by the layer kernels (skip flag, layer
+// coefficients) and copied back to the host for sp2_info.
+// ---------------------------------------------------------------------------------
+struct DevState {
+    int n, n_occ, n_padded, max_layers;
+    int precision, tile, have_bounds, want_energy;
+    int stopped;        // 1 once a stopping test held, a non-finite value appeared or the cap hit
+    int converged;
+    int layers;         // m
+    int status;         // device-side sp2_status
+    int skip;           // layer kernels of the current layer do nothing when set
+    int first_sign;     // first composed step of the refinement
+    int refine_src;     // ping-pong index of the state matrix that is refined
+    int pad0;
+    float coef[3];      // (alpha, beta, gamma) of the current layer: Y = alpha X^2 + beta X + gamma I
+    float rcoef[2][3];  // the two refinement layers
+    float pad1;
+    double eps, tol_tr, tol_id;
+    double emin, emax;
+    double asym;
+    double trace_d, frob_d, energy;
+    signed char sigma[SP2_MAX_LAYERS + 1];  // index n = layer n (sigma[0] = 0)
+    double iderr[SP2_MAX_LAYERS + 1];
+    double ns[SP2_MAX_LAYERS + 1];
+    double nx[SP2_MAX_LAYERS + 1];
+};
+
+// Upper-triangle tile enumeration shared by every kernel that works on (I <= J) tiles.
+// The T x T tile grid is cut into column strips of width G; strips are enumerated left
+// to right, and inside a strip the tiles go row by row.  Consecutive indices therefore
+// form compact G-wide blocks of rows, so workgroups that run at the same time on one
+// XCD share their row and column panels in that XCD's L2.
+__host__ __device__ inline void tile_of(int t, int T, int G, int* pi, int* pj) {
+    int s = 0, off = 0;
+    for (;;) {
+        int w = T - s * G < G ? T - s * G : G;
+        int cnt = s * G * w + w * (w + 1) / 2;
+        if (t < off + cnt) {
+            int u = t - off;
+            int sg = s * G;
+            if (u < sg * w) {
+                *pi = u / w;
+                *pj = sg + u % w;
+            } else {
+                u -= sg * w;
+                int i = 0;
+                while (u >= w - i) { u -= w - i; ++i; }
+                *pi = sg + i;
+                *pj = sg + i + u;
+            }
+            return;
+        }
+        off += cnt;
+        ++s;
+    }
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the MI355X; this maps the
+// hardware block index so that XCD x receives the contiguous tile range
+// [x*per, (x+1)*per).  Returns -1 for the (at most 7) surplus blocks.
+__device__ inline int xcd_tile_index(int b, int per, int ntiles) {
+    int t = (b & 7) * per + (b >> 3);
+    return t < ntiles ? t : -1;
+}
+
+inline int ntiles_upper(int T) { return T * (T + 1) / 2; }
+
+// ---------------------------------------------------------------------------------
+// Arguments of the squaring kernels: Y = alpha X^2 + beta X + gamma I, written to
+// both triangles (exactly symmetric), optionally split into half-precision planes, with
+// FP64 partial sums of Tr Y and ||Y||_F^2 per output tile.
+// ---------------------------------------------------------------------------------
+struct SquareArgs {
+    const void* x0;       // split modes: high plane of X (np x np, ld np); plain: X itself
+    const void* x1;       // split modes: low plane of X
+    const void* s_in;     // X in the state precision (beta term), ld = np
+    void* s_out;          // Y in the state precision, ld = ld_out
+    void* p0_out;         // split modes: planes of Y (ld np), or null
+    void* p1_out;
+    double* parts;        // 2 doubles per tile, or null
+    const float* coef;    // (alpha, beta, gamma)
+    const int* skip;      // null, or a flag that makes every workgroup return at once
+    int np;               // padded edge (multiple of the tile)
+    int ld_out;           // leading dimension of s_out
+    int n_valid;          // rows/cols >= n_valid of s_out are not written
+    int T;                // tiles per edge
+    int ntiles;           // T (T + 1) / 2
+    int per;              // ceil(ntiles / 8)
+    float out_scale;      // split modes: 2^-2s applied to the accumulated products
+    float in_scale;       // split modes: 2^s applied before splitting Y
+};
+
+// Host-side launchers (defined next to their kernels).
+hipError_t launch_square_split(int precision, int tile, const SquareArgs& a, hipStream_t s);
+hipError_t launch_square_plain(int precision, int tile, const SquareArgs& a, hipStream_t s);
+int square_split_grid(int tile, int np, int* T, int* ntiles, int* per);
+int square_plain_grid(int tile, int np, int* T, int* ntiles, int* per);
+
+// preparation / control kernels (k_prep.hip)
+hipError_t launch_state_init(DevState* st, const DevState& init, hipStream_t s);
+hipError_t launch_gershgorin(const double* h, int ldh, int n, double* blk, int* nblk, hipStream_t s);
+int gershgorin_blocks(int n);
+hipError_t launch_bounds(DevState* st, const double* blk, int nblk, hipStream_t s);
+hipError_t launch_init_np(const double* h, int ldh, DevState* st, int np, int precision, void* s_out,
+                          void* p0, void* p1, int scale_log2, double* parts, hipStream_t s);
+int init_tiles(int np);
+hipError_t launch_control_stride(DevState* st, const double* parts, int nparts, int stride, int layer,
+                                 hipStream_t s);
+hipError_t launch_select_f64(const DevState* st, const void* s0, const void* s1, int state_f64,
+                             double* out, int ld_out, int n_valid, int np, hipStream_t s);
+hipError_t launch_dstats(const double* d, int ldd, const double* h, int ldh, int n,
+                         double* parts, int* nparts, hipStream_t s);
+int dstats_blocks(int n);
+hipError_t launch_finalize(DevState* st, const double* dparts, int ndparts, const double* init_parts,
+                           int ninit, hipStream_t s);
+hipError_t launch_fill(double* d, int ldd, int n, double diag, hipStream_t s);
+hipError_t launch_split(const float* x, void* p0, void* p1, int np, int precision, int scale_log2,
+                        hipStream_t s);
+hipError_t launch_sum_parts(const double* parts, int nparts, double* out2, hipStream_t s);
+hipError_t launch_set3(float* dst, float a, float b, float c, hipStream_t s);
+hipError_t launch_mark_trivial(DevState* st, hipStream_t s);
+
+}  // namespace sp2

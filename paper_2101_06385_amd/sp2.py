@@ -1,0 +1,251 @@
+"""ctypes binding of libsp2 (C ABI in include/sp2.h).
+
+Argument marshalling only: every step of the density-matrix computation runs in the
+HIP kernels of libsp2.  PyTorch supplies device memory and the current stream.  The
+library is loaded on first use; if it has not been built this raises instead of
+falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libsp2.so")
+
+SP2_OK, SP2_EINVAL, SP2_ENONFINITE, SP2_ENOCONV, SP2_ENOTIDEMP, SP2_EDEVICE, SP2_ENOMEM = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENONFINITE", -3: "ENOCONV", -4: "ENOTIDEMP", -5: "EDEVICE",
+                -6: "ENOMEM"}
+FP64, FP32, FP16X2, BF16X2 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16x2": FP16X2, "bf16x2": BF16X2}
+MAX_LAYERS = 128
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int),
+        ("max_layers", ctypes.c_int),
+        ("eps", ctypes.c_double),
+        ("have_bounds", ctypes.c_int),
+        ("emin", ctypes.c_double),
+        ("emax", ctypes.c_double),
+        ("refine", ctypes.c_int),
+        ("scale_log2", ctypes.c_int),
+        ("want_energy", ctypes.c_int),
+        ("tile", ctypes.c_int),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("layers", ctypes.c_int),
+        ("converged", ctypes.c_int),
+        ("first_sign", ctypes.c_int),
+        ("n_padded", ctypes.c_int),
+        ("tile", ctypes.c_int),
+        ("emin", ctypes.c_double),
+        ("emax", ctypes.c_double),
+        ("trace", ctypes.c_double),
+        ("idem", ctypes.c_double),
+        ("energy", ctypes.c_double),
+        ("asym", ctypes.c_double),
+        ("sigma", ctypes.c_byte * MAX_LAYERS),
+        ("iderr", ctypes.c_double * MAX_LAYERS),
+        ("ns", ctypes.c_double * MAX_LAYERS),
+        ("nx", ctypes.c_double * MAX_LAYERS),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsp2.so (after torch, so that the HIP runtime torch ships is the one bound)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libsp2.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    import torch  # noqa: F401  (binds libamdhip64 first)
+
+    L = ctypes.CDLL(LIB_PATH)
+    c_int, c_double, c_size_t, c_void_p, c_float = (ctypes.c_int, ctypes.c_double, ctypes.c_size_t,
+                                                     ctypes.c_void_p, ctypes.c_float)
+    L.sp2_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.sp2_default_options.restype = None
+    L.sp2_strerror.argtypes = [c_int]
+    L.sp2_strerror.restype = ctypes.c_char_p
+    L.sp2_version.argtypes = []
+    L.sp2_version.restype = ctypes.c_char_p
+    L.sp2_workspace_size.argtypes = [c_int, ctypes.POINTER(Options)]
+    L.sp2_workspace_size.restype = c_size_t
+    L.sp2_density.argtypes = [c_void_p, c_int, c_void_p, c_int, c_int, c_int, c_double, ctypes.POINTER(Options),
+                              ctypes.POINTER(Info), c_void_p, c_size_t, c_void_p]
+    L.sp2_density.restype = c_int
+    L.sp2_query.argtypes = [c_void_p, c_int, ctypes.POINTER(Options), ctypes.POINTER(Info), c_void_p]
+    L.sp2_query.restype = c_int
+    L.sp2_square_padded.argtypes = [c_int, c_int, c_int]
+    L.sp2_square_padded.restype = c_int
+    L.sp2_square_workspace_size.argtypes = [c_int, c_int, c_int]
+    L.sp2_square_workspace_size.restype = c_size_t
+    L.sp2_square.argtypes = [c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_float, c_float, c_float,
+                             ctypes.POINTER(c_double), c_void_p, c_size_t, c_void_p]
+    L.sp2_square.restype = c_int
+    _lib = L
+    return L
+
+
+def _prec(p) -> int:
+    if isinstance(p, str):
+        return PRECISIONS[p.lower()]
+    return int(p)
+
+
+def options(precision="fp16x2", max_layers=100, eps=0.0, bounds=None, refine=True, scale_log2=-1,
+            want_energy=False, tile=0) -> Options:
+    o = Options()
+    lib().sp2_default_options(ctypes.byref(o))
+    o.precision = _prec(precision)
+    o.max_layers = int(max_layers)
+    o.eps = float(eps)
+    if bounds is not None:
+        o.have_bounds = 1
+        o.emin, o.emax = float(bounds[0]), float(bounds[1])
+    o.refine = 1 if refine else 0
+    o.scale_log2 = int(scale_log2)
+    o.want_energy = 1 if want_energy else 0
+    o.tile = int(tile)
+    return o
+
+
+def strerror(status: int) -> str:
+    return lib().sp2_strerror(int(status)).decode()
+
+
+def version() -> str:
+    return lib().sp2_version().decode()
+
+
+def workspace_size(n: int, opts: Optional[Options] = None) -> int:
+    return int(lib().sp2_workspace_size(int(n), ctypes.byref(opts) if opts is not None else None))
+
+
+def _stream_ptr(device, stream=None):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def alloc_workspace(nbytes: int, device):
+    """Device bytes for the library (256-byte aligned view of a torch allocation)."""
+    import torch
+
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + int(nbytes)]
+
+
+def info_dict(info: Info) -> dict:
+    m = max(0, min(int(info.layers) + 1, MAX_LAYERS))
+    return {
+        "status": int(info.status),
+        "status_name": STATUS_NAMES.get(int(info.status), "?"),
+        "layers": int(info.layers),
+        "converged": bool(info.converged),
+        "first_sign": int(info.first_sign),
+        "n_padded": int(info.n_padded),
+        "tile": int(info.tile),
+        "emin": float(info.emin),
+        "emax": float(info.emax),
+        "trace": float(info.trace),
+        "idem": float(info.idem),
+        "energy": float(info.energy),
+        "asym": float(info.asym),
+        "sigma": [int(info.sigma[i]) for i in range(m)],
+        "iderr": [float(info.iderr[i]) for i in range(m)],
+        "ns": [float(info.ns[i]) for i in range(m)],
+        "nx": [float(info.nx[i]) for i in range(m)],
+    }
+
+
+class SP2Error(RuntimeError):
+    def __init__(self, status, where="sp2"):
+        super().__init__("%s: %s (%d)" % (where, STATUS_NAMES.get(status, "?"), status))
+        self.status = status
+
+
+def density(h, n_occ: int, tol: float = 0.0, precision="fp16x2", max_layers=100, eps=0.0, bounds=None,
+            refine=True, scale_log2=-1, want_energy=False, tile=0, out=None, workspace=None, sync=True,
+            stream=None):
+    """D = theta(mu I - H) with Tr D = n_occ (Alg. 1) for a symmetric FP64 CUDA tensor H.
+
+    Returns (D, info) with info a dict (sync=True) or None (sync=False, nothing is
+    read back; use `query`).  Argument errors raise SP2Error; numerical outcomes are
+    reported in info["status"].
+    """
+    import torch
+
+    if not (isinstance(h, torch.Tensor) and h.is_cuda and h.dtype == torch.float64 and h.dim() == 2):
+        raise TypeError("H must be a 2-D float64 CUDA tensor")
+    n = h.shape[0]
+    if h.shape[1] != n or h.stride(1) != 1:
+        raise ValueError("H must be square with unit column stride")
+    opts = options(precision, max_layers, eps, bounds, refine, scale_log2, want_energy, tile)
+    need = workspace_size(n, opts)
+    if need == 0:
+        raise SP2Error(SP2_EINVAL, "sp2_workspace_size")
+    if workspace is None or workspace.numel() < need:
+        workspace = alloc_workspace(need, h.device)
+    if out is None:
+        out = torch.empty((n, n), dtype=torch.float64, device=h.device)
+    info = Info() if sync else None
+    st = lib().sp2_density(ctypes.c_void_p(h.data_ptr()), h.stride(0), ctypes.c_void_p(out.data_ptr()),
+                           out.stride(0), n, int(n_occ), float(tol), ctypes.byref(opts),
+                           ctypes.byref(info) if info is not None else None,
+                           ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                           _stream_ptr(h.device, stream))
+    # host-side argument errors leave info untouched (n_padded == 0); the device-side
+    # symmetry check also reports EINVAL but fills info and writes D
+    if st in (SP2_EDEVICE, SP2_ENOMEM) or (st == SP2_EINVAL and (info is None or int(info.n_padded) == 0)):
+        raise SP2Error(st, "sp2_density")
+    return out, (info_dict(info) if info is not None else None)
+
+
+def query(workspace, n, precision="fp16x2", stream=None, device=None, **kw) -> dict:
+    opts = options(precision, **kw)
+    info = Info()
+    lib().sp2_query(ctypes.c_void_p(workspace.data_ptr()), int(n), ctypes.byref(opts), ctypes.byref(info),
+                    _stream_ptr(device or workspace.device, stream))
+    return info_dict(info)
+
+
+def square(x, alpha=1.0, beta=0.0, gamma=0.0, precision="fp16x2", tile=0, scale_log2=-1, workspace=None,
+           want_sums=True, stream=None):
+    """One layer Y = alpha X^2 + beta X + gamma I of a symmetric n x n CUDA tensor X (FP32 for
+    the FP32/split modes, FP64 for FP64).  Returns (Y, (Tr Y, ||Y||_F^2) or None)."""
+    import torch
+
+    p = _prec(precision)
+    n = x.shape[0]
+    L = lib()
+    np_ = L.sp2_square_padded(n, p, int(tile))
+    dt = torch.float64 if p == FP64 else torch.float32
+    if x.dtype != dt:
+        raise TypeError("X must be %s for this precision" % dt)
+    xp = torch.zeros((np_, np_), dtype=dt, device=x.device)
+    xp[:n, :n] = x
+    yp = torch.empty_like(xp)
+    need = L.sp2_square_workspace_size(n, p, int(tile))
+    if workspace is None or workspace.numel() < need:
+        workspace = alloc_workspace(need, x.device)
+    sums = (ctypes.c_double * 2)()
+    st = L.sp2_square(ctypes.c_void_p(xp.data_ptr()), ctypes.c_void_p(yp.data_ptr()), n, p, int(tile),
+                      int(scale_log2), float(alpha), float(beta), float(gamma), sums if want_sums else None,
+                      ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr(x.device, stream))
+    if st != SP2_OK:
+        raise SP2Error(st, "sp2_square")
+    return yp[:n, :n], ((sums[0], sums[1]) if want_sums else None)

@@ -1,0 +1,122 @@
+"""The C ABI library loads and exports every symbol that include/sp2.h declares, and its
+host-only entry points (defaults, status strings, workspace sizing, argument checks
+that return before any device work) behave as documented.  No GPU needed."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2101_06385_amd import sp2
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sp2.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(sp2.LIB_PATH), reason="libsp2.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sp2_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for want in ("sp2_density", "sp2_workspace_size", "sp2_default_options", "sp2_strerror", "sp2_query",
+                 "sp2_square"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(sp2.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """sizeof/offsetof of the ABI structs as the C compiler lays them out."""
+    import shutil
+    import subprocess
+
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stddef.h>\n#include <stdio.h>\n#include "sp2.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(sp2_options), sizeof(sp2_info),"
+        " offsetof(sp2_options, tile), offsetof(sp2_info, sigma), offsetof(sp2_info, iderr),"
+        " offsetof(sp2_info, nx));return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [ctypes.sizeof(sp2.Options), ctypes.sizeof(sp2.Info), sp2.Options.tile.offset,
+            sp2.Info.sigma.offset, sp2.Info.iderr.offset, sp2.Info.nx.offset]
+    assert got == want
+
+
+def test_defaults_and_strings():
+    o = sp2.Options()
+    sp2.lib().sp2_default_options(ctypes.byref(o))
+    assert o.precision == sp2.FP16X2 and o.max_layers == 100 and o.refine == 1 and o.scale_log2 == -1
+    assert o.eps == 0.0 and o.have_bounds == 0 and o.tile == 0
+    for st in range(-6, 1):
+        assert isinstance(sp2.strerror(st), str) and sp2.strerror(st)
+    assert "gfx950" in sp2.version()
+
+
+def test_workspace_size_scales_with_n_and_precision():
+    sizes = {}
+    for p in ("fp64", "fp32", "fp16x2", "bf16x2"):
+        o = sp2.options(precision=p)
+        sizes[p] = [sp2.workspace_size(n, o) for n in (1, 100, 1000, 8192)]
+        assert all(s > 0 for s in sizes[p])
+        assert sizes[p] == sorted(sizes[p])
+    np_ = 8192
+    # split mode: two FP32 states + four half planes + FP64 refinement input and output
+    assert sizes["fp16x2"][-1] >= np_ * np_ * (2 * 4 + 4 * 2 + 2 * 8)
+    assert sp2.workspace_size(0, sp2.options()) == 0
+
+
+def test_invalid_options_give_zero_workspace():
+    assert sp2.workspace_size(100, sp2.options(max_layers=200)) == 0
+    assert sp2.workspace_size(100, sp2.options(tile=96)) == 0
+    assert sp2.workspace_size(100, sp2.options(precision="fp64", tile=256)) == 0
+    assert sp2.workspace_size(100, sp2.options(bounds=(1.0, -1.0))) == 0
+    assert sp2.workspace_size(100, sp2.options(precision="fp16x2", scale_log2=15)) == 0
+
+
+def test_argument_errors_return_before_device_work():
+    L = sp2.lib()
+    o = sp2.options()
+    fake = ctypes.c_void_p(256)   # never dereferenced: every call below fails validation first
+    cases = [
+        dict(n=0, n_occ=0, ldh=1, ldd=1),
+        dict(n=10, n_occ=-1, ldh=10, ldd=10),
+        dict(n=10, n_occ=11, ldh=10, ldd=10),
+        dict(n=10, n_occ=5, ldh=9, ldd=10),
+        dict(n=10, n_occ=5, ldh=10, ldd=9),
+    ]
+    for c in cases:
+        st = L.sp2_density(fake, c["ldh"], fake, c["ldd"], c["n"], c["n_occ"], 0.0, ctypes.byref(o), None,
+                           fake, 1 << 40, None)
+        assert st == sp2.SP2_EINVAL, c
+    # null pointers
+    assert L.sp2_density(None, 10, fake, 10, 10, 5, 0.0, ctypes.byref(o), None, fake, 1 << 40, None) == sp2.SP2_EINVAL
+    # misaligned workspace
+    assert L.sp2_density(fake, 10, fake, 10, 10, 5, 0.0, ctypes.byref(o), None, ctypes.c_void_p(260), 1 << 40,
+                         None) == sp2.SP2_EINVAL
+    # workspace too small
+    assert L.sp2_density(fake, 10, fake, 10, 10, 5, 0.0, ctypes.byref(o), None, fake, 16, None) == sp2.SP2_ENOMEM
+    # bad options
+    bad = sp2.options(max_layers=500)
+    assert L.sp2_density(fake, 10, fake, 10, 10, 5, 0.0, ctypes.byref(bad), None, fake, 1 << 40,
+                         None) == sp2.SP2_EINVAL
+
+
+def test_square_padding_helpers():
+    L = sp2.lib()
+    assert L.sp2_square_padded(300, sp2.FP16X2, 64) == 320
+    assert L.sp2_square_padded(300, sp2.FP16X2, 256) == 512
+    assert L.sp2_square_padded(8192, sp2.FP16X2, 0) == 8192
+    assert L.sp2_square_workspace_size(300, sp2.FP16X2, 64) > 4 * 320 * 320
