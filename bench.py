@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""SP2 density-matrix benchmark on one AMD Instinct MI355X (gfx950).
+
+One step is one call of the whole path through the C ABI (sp2_density): Gershgorin
+bounds, input layer, the Alg. 1 layers with the dual-FP16 squaring of Alg. 2, the FP64
+refinement layer and the final checks, on the N = 8192 small-gap stress Hamiltonian
+(25% occupation, 0.2 eV gap, eigenvalues uniform in [-25, 25] eV) resident in HBM.
+
+Reported (one JSON line on stdout; progress on stderr):
+  value            executed MFMA TFLOP/s of the layer loop: (m - 1) squarings x 3 N^2 (N + 1)
+                   FLOP (three half-precision products over the upper triangle) divided by
+                   the loop time measured with HIP events (the paper's rate also leaves out
+                   set-up and the refinement layer)
+  ms_per_step      time-to-D of one full call, H resident on the device
+  roofline         the squaring kernel against the dense FP16 matrix peak
+  fp64             the same computation with FP64 squarings on the GPU (speed comparison)
+  accuracy         ||D - D_ref||_F and |Tr D - N_occ| with D_ref the exact projector
+  cpu_baseline     the CPU oracle (FP64 NumPy Alg. 1) on a bounded sample of the workload
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP16_TFLOPS = 2500.0     # MI355X dense FP16/BF16 matrix peak
+PEAK_FP64_TFLOPS = 78.6       # MI355X FP64 matrix peak
+METRIC = "SP2 TFLOP/s + time-to-D at N=8192, mixed vs FP64, at stated ‖D−D_ref‖_F"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def flop_split_layer(n):
+    """Three half-precision products restricted to the upper triangle (with diagonal)."""
+    return 3.0 * 2.0 * n * (n * (n + 1) / 2.0)
+
+
+def flop_plain_layer(n):
+    """One FP32/FP64 product restricted to the upper triangle (with diagonal)."""
+    return 2.0 * n * (n * (n + 1) / 2.0)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--precision", default="fp16x2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--gen-device", default="cuda", help="where the QR of the workload generator runs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the path runs on one MI355X); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2101_06385_amd import sp2, workloads
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    t0 = time.perf_counter()
+    gen_dev = None if args.gen_device == "cpu" else "cuda:0"
+    try:
+        w = workloads.config3(n=n, device=gen_dev)
+    except Exception as e:  # pragma: no cover - fall back to LAPACK on the host
+        log("device QR failed (%s); generating on the host" % e)
+        w = workloads.config3(n=n)
+    log("workload %s generated in %.1f s" % (w.name, time.perf_counter() - t0))
+    h = torch.from_numpy(w.h).to(dev)
+    d = torch.empty_like(h)
+    opts = sp2.options(args.precision)
+    ws = sp2.alloc_workspace(sp2.workspace_size(n, opts), dev)
+    torch.cuda.synchronize()
+
+    def step():
+        sp2.density(h, w.n_occ, precision=args.precision, out=d, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t_start) * 1e3 / args.steps
+    log("time-to-D %.2f ms per step" % ms_per_step)
+
+    # one more call with HIP events between the kernels: loop time and squaring kernel time
+    _, info, tm = sp2.density(h, w.n_occ, precision=args.precision, out=d, workspace=ws, timed=True)
+    k = tm["squarings"]
+    sq = [t for t in tm["square_ms"][:k]]
+    f_layer = flop_split_layer(n) if args.precision in ("fp16x2", "bf16x2") else flop_plain_layer(n)
+    loop_ms = tm["loop_active_ms"]
+    value = k * f_layer / (loop_ms * 1e-3) / 1e12
+    paper_rate = k * (4.0 if args.precision in ("fp16x2", "bf16x2") else 2.0) * n ** 3 / (loop_ms * 1e-3) / 1e12
+    sq_mean = float(np.mean(sq)) if sq else float("nan")
+    achieved = f_layer / (sq_mean * 1e-3) / 1e12
+    peak = PEAK_FP16_TFLOPS if args.precision in ("fp16x2", "bf16x2") else (
+        PEAK_FP64_TFLOPS if args.precision == "fp64" else 157.3)
+    log("layers m=%d squarings=%d loop %.2f ms (%.1f TFLOP/s) square kernel %.3f ms (%.1f TFLOP/s) "
+        "refine %.2f ms status %s" % (info["layers"], k, loop_ms, value, sq_mean, achieved, tm["refine_ms"],
+                                       info["status_name"]))
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16" if args.precision == "fp16x2" else ("bf16" if args.precision == "bf16x2" else
+                                                           ("f64" if args.precision == "fp64" else "f32")),
+        "data": "synthetic",
+        "config": {
+            "workload": "small-gap stress Hamiltonian N=%d: H = Q diag(eps) Q^T, Haar Q, 25%% occupation, "
+                        "0.2 eV gap, eigenvalues uniform in [-25,25] eV; Gershgorin bounds" % n,
+            "n": n, "n_occ": w.n_occ, "precision": args.precision, "accumulate": "f32",
+            "layers": info["layers"], "squarings": k, "tile": info["tile"], "n_padded": info["n_padded"],
+        },
+        "time_to_d_ms": round(ms_per_step, 3),
+        "loop_ms": round(loop_ms, 3),
+        "refine_ms": round(tm["refine_ms"], 3),
+        "prep_ms": round(tm["prep_ms"], 3),
+        "paper_convention_tflops": round(paper_rate, 3),
+        "status": info["status_name"],
+        "trace_error": abs(info["trace"] - w.n_occ),
+        "idempotency": info["idem"],
+        "roofline": {
+            "bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None,
+            "kernel": "k_square_split<_Float16,256,2,4>" if n > 2048 and args.precision == "fp16x2" else "square",
+            "flop_per_launch": f_layer, "launch_ms": round(sq_mean, 4),
+        },
+    }
+
+    if not args.no_fp64:
+        d64 = torch.empty_like(h)
+        o64 = sp2.options("fp64")
+        ws64 = sp2.alloc_workspace(sp2.workspace_size(n, o64), dev)
+        sp2.density(h, w.n_occ, precision="fp64", out=d64, workspace=ws64)      # warm
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, i64 = sp2.density(h, w.n_occ, precision="fp64", out=d64, workspace=ws64)
+        torch.cuda.synchronize()
+        ttd64 = (time.perf_counter() - t1) * 1e3
+        _, i64, tm64 = sp2.density(h, w.n_occ, precision="fp64", out=d64, workspace=ws64, timed=True)
+        k64 = tm64["squarings"]
+        v64 = k64 * flop_plain_layer(n) / (tm64["loop_active_ms"] * 1e-3) / 1e12
+        out["fp64"] = {"time_to_d_ms": round(ttd64, 3), "tflops": round(v64, 3), "layers": i64["layers"],
+                       "status": i64["status_name"], "trace_error": abs(i64["trace"] - w.n_occ),
+                       "speedup_mixed_vs_fp64": round(ttd64 / ms_per_step, 3),
+                       "frac_of_fp64_peak": round(v64 / PEAK_FP64_TFLOPS, 4)}
+        log("fp64: time-to-D %.1f ms, %.1f TFLOP/s, layers %d, %s" % (ttd64, v64, i64["layers"], i64["status_name"]))
+    else:
+        d64 = None
+
+    if not args.no_cpu_baseline:
+        # CPU leg: the oracle (test infrastructure) on a bounded sample, plus the exact
+        # projector for the accuracy of the GPU results.
+        from oracle import dm as odm
+        from oracle import sp2 as osp2
+
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([p.get("num_threads", 0) for p in threadpool_info()] + [1])
+        except Exception:  # pragma: no cover
+            cores = os.cpu_count()
+        layers = 2
+        tc = time.perf_counter()
+        osp2.sp2_alg1(w.h, w.n_occ, max_layers=layers, refine=False)
+        tcpu = time.perf_counter() - tc
+        cpu_rate = layers * 2.0 * n ** 3 / tcpu / 1e12
+        out["cpu_baseline"] = {
+            "value": round(cpu_rate, 4), "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+            "sample": "first %d FP64 layers of Alg. 1 (oracle.sp2.sp2_alg1, NumPy/OpenBLAS, including its "
+                      "Gershgorin bounds and input layer) on the same N=%d Hamiltonian, %.1f s; rate credits "
+                      "2N^3 per layer" % (layers, n, tcpu),
+            "time_to_d_est_s": round(tcpu / layers * (info["layers"] + 2), 1),
+        }
+        log("cpu oracle: %.3f TFLOP/s on %d threads (%.1f s)" % (cpu_rate, cores, tcpu))
+        d_ref = odm.dm_construct(w.q, w.eps, w.n_occ)
+        acc = {"fro_error": float(np.linalg.norm(d.cpu().numpy() - d_ref)),
+               "fro_bound": 1e-3 * math.sqrt(n), "trace_error": abs(info["trace"] - w.n_occ)}
+        if d64 is not None:
+            acc["fro_error_fp64"] = float(np.linalg.norm(d64.cpu().numpy() - d_ref))
+        out["accuracy"] = acc
+        log("accuracy: %s" % acc)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

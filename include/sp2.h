@@ -129,6 +129,29 @@ int sp2_density(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ
                 const sp2_options* opt, sp2_info* info, void* dWork, size_t work_bytes,
                 void* stream);
 
+/* Phase and per-layer durations of one sp2_density call, from HIP events on `stream`. */
+typedef struct {
+    double total_ms;       /* first kernel of the call .. last kernel */
+    double prep_ms;        /* state init, spectral bounds, input layer */
+    double loop_ms;        /* every layer launched (max_layers control + squaring pairs) */
+    double loop_active_ms; /* start of the loop .. end of the last squaring that ran (S_{m-1}) */
+    double refine_ms;      /* widening to FP64 and the two refinement layers */
+    double final_ms;       /* final reductions and acceptance test */
+    int squarings;         /* squaring layers that ran: m - 1 on convergence */
+    int pad;
+    float square_ms[SP2_MAX_LAYERS];   /* squaring kernel of layer n at index n - 1 */
+    float refine_square_ms[2];         /* the two FP64 refinement layers */
+} sp2_timing;
+
+/*
+ * sp2_density_timed -- sp2_density with HIP events recorded between the kernels it
+ * enqueues (same kernels, same results); synchronizes and fills *timing (host).  For
+ * benchmarks: event creation makes it slower to call than sp2_density.
+ */
+int sp2_density_timed(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ, double tol,
+                      const sp2_options* opt, sp2_info* info, void* dWork, size_t work_bytes,
+                      void* stream, sp2_timing* timing);
+
 /*
  * sp2_query -- synchronize `stream` and read the outcome of the last sp2_density call
  * that used this workspace (with the same n and options) into *info.  Returns the

@@ -78,7 +78,7 @@ __global__ void k_state_init(DevState* st, StateParams p) {
         st->skip = 0;
         st->first_sign = 0;
         st->refine_src = 0;
-        st->pad0 = 0;
+        st->ran = 0;
         for (int i = 0; i < 3; ++i) st->coef[i] = 0.f;
         for (int i = 0; i < 6; ++i) st->rcoef[i / 3][i % 3] = 0.f;
         st->pad1 = 0.f;
@@ -269,10 +269,14 @@ __global__ __launch_bounds__(kThreads) void k_init(const double* __restrict__ h,
 // kernels receive sigma_n as coefficients (or a skip flag once a test has held).
 // ---------------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_control(DevState* st, const double* __restrict__ parts,
-                                                      int nparts, int stride, int layer) {
+                                                      int nparts, int stride, int layer,
+                                                      volatile int* __restrict__ host_flag) {
     __shared__ double sh[2 * kThreads];
     if (st->stopped) {
-        if (threadIdx.x == 0) st->skip = 1;
+        if (threadIdx.x == 0) {
+            st->skip = 1;
+            if (host_flag) *host_flag = 1;
+        }
         return;
     }
     double v[2] = {0.0, 0.0};
@@ -309,12 +313,14 @@ __global__ __launch_bounds__(kThreads) void k_control(DevState* st, const double
             st->coef[2] = 0.f;
             st->skip = 0;
             st->layers = n;
+            st->ran = n;
             return;
         }
         stop = true;
     }
     // stopping: refine S_{n-1}
     st->stopped = 1;
+    if (host_flag) *host_flag = 1;   // lets a host that polls stop enqueueing layers
     st->skip = 1;
     st->converged = conv ? 1 : 0;
     st->layers = (conv || !isfinite(n_s) || !isfinite(n_x)) ? n : n - 1;
@@ -538,8 +544,9 @@ hipError_t launch_init_np(const double* h, int ldh, DevState* st, int np, int pr
 }
 
 hipError_t launch_control_stride(DevState* st, const double* parts, int nparts, int stride, int layer,
-                                 hipStream_t s) {
-    hipLaunchKernelGGL(k_control, dim3(1), dim3(kThreads), 0, s, st, parts, nparts, stride, layer);
+                                 int* host_flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_control, dim3(1), dim3(kThreads), 0, s, st, parts, nparts, stride, layer,
+                       (volatile int*)host_flag);
     return hipGetLastError();
 }
 

@@ -229,7 +229,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_split(SquareArgs a) {
                 for (int e = 0; e < 4; ++e) {
                     const float x = acc[m][n][4 * g + e] * osc;
                     float y = (beta != 0.f) ? fmaf(alpha, x, beta * sv[e]) : alpha * x;
-                    if (row0 + e == col) y += gamma;
+                    if (row0 + e == col && col < a.n_real) y += gamma;
                     v[e] = y;
                     const float ys = y * isc;
                     h0[e] = (T16)ys;
@@ -295,7 +295,8 @@ template <typename E>
 struct PlainOps;
 
 // FP64: v_mfma_f64_16x16x4_f64.  Lane l holds A[l%16][l/16], B[l/16][l%16]; the
-// result block element (4*(l/16) + e, l%16) is acc[e].
+// result block element (4*e + l/16, l%16) is acc[e] (rows interleaved across the
+// four 16-lane groups).
 template <>
 struct PlainOps<double> {
     typedef f64x4 accv;
@@ -308,7 +309,7 @@ struct PlainOps<double> {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
     // row / col of accumulator r of this lane inside a block
-    __device__ static inline int arow(int lane, int r) { return 4 * (lane >> 4) + r; }
+    __device__ static inline int arow(int lane, int r) { return 4 * r + (lane >> 4); }
     __device__ static inline int acol(int lane) { return lane & 15; }
     __device__ static inline int frow(int lane) { return lane & 15; }
     __device__ static inline int fk(int lane) { return lane >> 4; }
@@ -440,7 +441,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_plain(SquareArgs a) {
                 if (diag && row > col) continue;
                 const E xv = acc[m][n][r];
                 E y = (beta != (E)0) ? alpha * xv + beta * si[(size_t)col * np + row] : alpha * xv;
-                if (row == col) y += gamma;
+                if (row == col && col < a.n_real) y += gamma;
                 if (row < nv && col < nv) {
                     so[(size_t)row * ldo + col] = y;
                     if (row != col) so[(size_t)col * ldo + row] = y;

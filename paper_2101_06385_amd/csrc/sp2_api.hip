@@ -132,6 +132,86 @@ void fill_info(const DevState& st, const Plan* p, sp2_info* info) {
         if ((expr) != hipSuccess) return SP2_EDEVICE;   \
     } while (0)
 
+// Pinned, device-mapped int that the control kernel sets when Alg. 1 stops.
+struct HostFlag {
+    bool on = false, ok = true;
+    int* host = nullptr;
+    int* dev = nullptr;
+    explicit HostFlag(bool enable) : on(enable) {
+        if (!on) return;
+        ok = hipHostMalloc((void**)&host, 64, hipHostMallocMapped) == hipSuccess;
+        if (ok) {
+            *host = 0;
+            ok = hipHostGetDevicePointer((void**)&dev, host, 0) == hipSuccess;
+        }
+    }
+    ~HostFlag() {
+        if (host) (void)hipHostFree(host);
+    }
+};
+
+struct ChunkEvents {
+    bool ok = true;
+    int count = 0;
+    hipEvent_t ev[SP2_MAX_LAYERS + 2] = {};
+    ChunkEvents(bool enable, int n) : count(enable ? n : 0) {
+        for (int i = 0; i < count; ++i)
+            ok = ok && hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) == hipSuccess;
+    }
+    ~ChunkEvents() {
+        for (int i = 0; i < count; ++i)
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
+    }
+};
+
+// HIP events recorded between the kernels of one call (timed entry point only).
+struct Events {
+    bool on = false, ok = true;
+    int layers = 0, launched = 0;
+    hipEvent_t start = nullptr, prep = nullptr, loop_end = nullptr, end = nullptr;
+    hipEvent_t ref[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t sq_b[SP2_MAX_LAYERS + 1] = {}, sq_e[SP2_MAX_LAYERS + 1] = {};
+    Events(bool enable, int max_layers) : on(enable), layers(max_layers) {
+        if (!on) return;
+        hipEvent_t* all[] = {&start, &prep, &loop_end, &end, &ref[0], &ref[1], &ref[2]};
+        for (hipEvent_t* e : all) ok = ok && hipEventCreate(e) == hipSuccess;
+        for (int k = 1; k <= layers; ++k)
+            ok = ok && hipEventCreate(&sq_b[k]) == hipSuccess && hipEventCreate(&sq_e[k]) == hipSuccess;
+    }
+    ~Events() {
+        if (!on) return;
+        hipEvent_t all[] = {start, prep, loop_end, end, ref[0], ref[1], ref[2]};
+        for (hipEvent_t e : all)
+            if (e) (void)hipEventDestroy(e);
+        for (int k = 1; k <= layers; ++k) {
+            if (sq_b[k]) (void)hipEventDestroy(sq_b[k]);
+            if (sq_e[k]) (void)hipEventDestroy(sq_e[k]);
+        }
+    }
+    hipError_t rec(hipEvent_t e, hipStream_t s) { return on ? hipEventRecord(e, s) : hipSuccess; }
+    static double ms(hipEvent_t a, hipEvent_t b) {
+        float t = 0.f;
+        return hipEventElapsedTime(&t, a, b) == hipSuccess ? (double)t : -1.0;
+    }
+    hipError_t fill(sp2_timing* t, int ran, bool trivial) {
+        hipError_t e = hipEventSynchronize(end);
+        if (e != hipSuccess) return e;
+        memset(t, 0, sizeof(*t));
+        t->total_ms = ms(start, end);
+        t->squarings = ran;
+        if (trivial) return hipSuccess;
+        t->prep_ms = ms(start, prep);
+        t->loop_ms = ms(prep, loop_end);
+        t->loop_active_ms = (ran > 0 && ran <= launched) ? ms(prep, sq_e[ran]) : 0.0;
+        t->refine_ms = ms(loop_end, ref[2]);
+        t->final_ms = ms(ref[2], end);
+        for (int k = 1; k <= launched; ++k) t->square_ms[k - 1] = (float)ms(sq_b[k], sq_e[k]);
+        t->refine_square_ms[0] = (float)ms(ref[0], ref[1]);
+        t->refine_square_ms[1] = (float)ms(ref[1], ref[2]);
+        return hipSuccess;
+    }
+};
+
 }  // namespace
 
 extern "C" {
@@ -175,8 +255,9 @@ size_t sp2_workspace_size(int n, const sp2_options* opt) {
     return p.total;
 }
 
-int sp2_density(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ, double tol,
-                const sp2_options* opt, sp2_info* info, void* dWork, size_t work_bytes, void* stream) {
+static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ, double tol,
+                       const sp2_options* opt, sp2_info* info, void* dWork, size_t work_bytes, void* stream,
+                       sp2_timing* timing) {
     Opts o;
     if (!read_opts(opt, &o)) return SP2_EINVAL;
     if (n <= 0 || ldh < n || ldd < n || n_occ < 0 || n_occ > n || !dH || !dD || !dWork) return SP2_EINVAL;
@@ -188,6 +269,9 @@ int sp2_density(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ
     hipStream_t s = (hipStream_t)stream;
     char* ws = (char*)dWork;
     DevState* st = (DevState*)ws;
+    Events ev(timing != nullptr, o.max_layers);
+    if (!ev.ok) return SP2_EDEVICE;
+    SP2_TRY(ev.rec(ev.start, s));
 
     DevState init;
     memset(&init, 0, sizeof(init));
@@ -228,6 +312,7 @@ int sp2_density(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ
         void* P[2][2] = {{p.split ? ws + p.off_p[0][0] : nullptr, p.split ? ws + p.off_p[0][1] : nullptr},
                          {p.split ? ws + p.off_p[1][0] : nullptr, p.split ? ws + p.off_p[1][1] : nullptr}};
         SP2_TRY(launch_init_np(dH, ldh, st, p.np, o.precision, S[0], P[0][0], P[0][1], p.scale_log2, init_parts, s));
+        SP2_TRY(ev.rec(ev.prep, s));
 
         SquareArgs a;
         memset(&a, 0, sizeof(a));
@@ -237,16 +322,36 @@ int sp2_density(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ
         a.np = p.np;
         a.ld_out = p.np;
         a.n_valid = p.np;
+        a.n_real = n;
         a.T = p.main_T;
         a.ntiles = p.main_tiles;
         a.per = p.main_per;
         a.out_scale = ldexpf(1.f, -2 * p.scale_log2);
         a.in_scale = ldexpf(1.f, p.scale_log2);
+        // Synchronous calls poll a mapped host flag that the control kernel sets when Alg. 1
+        // stops, so that no layers are enqueued long after convergence: layers go out in
+        // chunks, two chunks ahead of the one the host waits for.  Asynchronous calls
+        // enqueue every layer up to max_layers (later ones return at once).
+        HostFlag flag(info != nullptr || timing != nullptr);
+        if (!flag.ok) return SP2_EDEVICE;
+        const int chunk = n >= 4096 ? 2 : (n >= 1024 ? 4 : 8);
+        ChunkEvents cev(flag.on, (o.max_layers + chunk) / chunk + 1);
+        if (!cev.ok) return SP2_EDEVICE;
+        int waited = 0;   // chunks whose completion the host has observed
         for (int layer = 1; layer <= o.max_layers + 1; ++layer) {
+            if (flag.on && layer > 1 && (layer - 1) % chunk == 0) {
+                const int c = (layer - 1) / chunk;          // chunk about to start
+                SP2_TRY(hipEventRecord(cev.ev[c - 1], s));  // end of chunk c - 1
+                if (c >= 2) {
+                    SP2_TRY(hipEventSynchronize(cev.ev[c - 2]));
+                    waited = c - 1;
+                    if (*flag.host) break;
+                }
+            }
             if (layer == 1)
-                SP2_TRY(launch_control_stride(st, init_parts, p.init_tiles, 3, layer, s));
+                SP2_TRY(launch_control_stride(st, init_parts, p.init_tiles, 3, layer, flag.dev, s));
             else
-                SP2_TRY(launch_control_stride(st, main_parts, p.main_tiles, 2, layer, s));
+                SP2_TRY(launch_control_stride(st, main_parts, p.main_tiles, 2, layer, flag.dev, s));
             if (layer > o.max_layers) break;
             const int in = (layer - 1) & 1, out = layer & 1;
             a.x0 = p.split ? P[in][0] : S[in];
@@ -255,15 +360,21 @@ int sp2_density(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ
             a.s_out = S[out];
             a.p0_out = P[out][0];
             a.p1_out = P[out][1];
+            ev.launched = layer;
+            SP2_TRY(ev.rec(ev.sq_b[layer], s));
             if (p.split)
                 SP2_TRY(launch_square_split(o.precision, p.tile_main, a, s));
             else
                 SP2_TRY(launch_square_plain(o.precision, p.tile_main, a, s));
+            SP2_TRY(ev.rec(ev.sq_e[layer], s));
         }
+        (void)waited;
+        SP2_TRY(ev.rec(ev.loop_end, s));
         if (o.refine) {
             double* s64 = (double*)(ws + p.off_s64);
             double* y = (double*)(ws + p.off_y);
             SP2_TRY(launch_select_f64(st, S[0], S[1], o.precision == SP2_FP64, s64, p.np, p.np, p.np, s));
+            SP2_TRY(ev.rec(ev.ref[0], s));
             SquareArgs r;
             memset(&r, 0, sizeof(r));
             r.np = p.np;
@@ -275,8 +386,10 @@ int sp2_density(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ
             r.s_out = y;
             r.ld_out = p.np;
             r.n_valid = p.np;
+            r.n_real = n;
             r.coef = st->rcoef[0];
             SP2_TRY(launch_square_plain(SP2_FP64, p.tile_ref, r, s));
+            SP2_TRY(ev.rec(ev.ref[1], s));
             r.x0 = y;
             r.s_in = y;
             r.s_out = dD;
@@ -284,20 +397,43 @@ int sp2_density(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ
             r.n_valid = n;
             r.coef = st->rcoef[1];
             SP2_TRY(launch_square_plain(SP2_FP64, p.tile_ref, r, s));
+            SP2_TRY(ev.rec(ev.ref[2], s));
         } else {
             SP2_TRY(launch_select_f64(st, S[0], S[1], o.precision == SP2_FP64, dD, ldd, n, p.np, s));
+            SP2_TRY(ev.rec(ev.ref[0], s));
+            SP2_TRY(ev.rec(ev.ref[1], s));
+            SP2_TRY(ev.rec(ev.ref[2], s));
         }
         int nd = 0;
         SP2_TRY(launch_dstats(dD, ldd, o.want_energy ? dH : nullptr, ldh, n, dstats, &nd, s));
         SP2_TRY(launch_finalize(st, dstats, nd, init_parts, p.init_tiles, s));
     }
-    if (!info) return SP2_OK;
+    SP2_TRY(ev.rec(ev.end, s));
+    if (!info && !timing) return SP2_OK;
     DevState host;
     SP2_TRY(hipStreamSynchronize(s));
     SP2_TRY(hipMemcpy(&host, st, sizeof(DevState), hipMemcpyDeviceToHost));
-    fill_info(host, &p, info);
+    if (info) fill_info(host, &p, info);
+    if (timing) {
+        const bool trivial = (n_occ == 0 || n_occ == n);
+        SP2_TRY(ev.fill(timing, trivial ? 0 : host.ran, trivial));
+    }
     return host.status;
 }
+
+int sp2_density(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ, double tol,
+                const sp2_options* opt, sp2_info* info, void* dWork, size_t work_bytes, void* stream) {
+    return run_density(dH, ldh, dD, ldd, n, n_occ, tol, opt, info, dWork, work_bytes, stream, nullptr);
+}
+
+int sp2_density_timed(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ, double tol,
+                      const sp2_options* opt, sp2_info* info, void* dWork, size_t work_bytes, void* stream,
+                      sp2_timing* timing) {
+    if (!timing) return SP2_EINVAL;
+    return run_density(dH, ldh, dD, ldd, n, n_occ, tol, opt, info, dWork, work_bytes, stream, timing);
+}
+
+
 
 int sp2_query(const void* dWork, int n, const sp2_options* opt, sp2_info* info, void* stream) {
     Opts o;
@@ -366,6 +502,7 @@ int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int sca
     a.np = np;
     a.ld_out = np;
     a.n_valid = np;
+    a.n_real = n;
     a.T = T;
     a.ntiles = nt;
     a.per = per;

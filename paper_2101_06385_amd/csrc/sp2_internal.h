@@ -24,7 +24,7 @@ struct DevState {
     int skip;           // layer kernels of the current layer do nothing when set
     int first_sign;     // first composed step of the refinement
     int refine_src;     // ping-pong index of the state matrix that is refined
-    int pad0;
+    int ran;            // squaring layers that ran (the last layer whose control let it run)
     float coef[3];      // (alpha, beta, gamma) of the current layer: Y = alpha X^2 + beta X + gamma I
     float rcoef[2][3];  // the two refinement layers
     float pad1;
@@ -96,6 +96,7 @@ struct SquareArgs {
     int np;               // padded edge (multiple of the tile)
     int ld_out;           // leading dimension of s_out
     int n_valid;          // rows/cols >= n_valid of s_out are not written
+    int n_real;           // logical edge: the gamma I term stops here so the padding stays zero
     int T;                // tiles per edge
     int ntiles;           // T (T + 1) / 2
     int per;              // ceil(ntiles / 8)
@@ -118,7 +119,7 @@ hipError_t launch_init_np(const double* h, int ldh, DevState* st, int np, int pr
                           void* p0, void* p1, int scale_log2, double* parts, hipStream_t s);
 int init_tiles(int np);
 hipError_t launch_control_stride(DevState* st, const double* parts, int nparts, int stride, int layer,
-                                 hipStream_t s);
+                                 int* host_flag, hipStream_t s);
 hipError_t launch_select_f64(const DevState* st, const void* s0, const void* s1, int state_f64,
                              double* out, int ld_out, int n_valid, int np, hipStream_t s);
 hipError_t launch_dstats(const double* d, int ldd, const double* h, int ldh, int n,

@@ -58,6 +58,21 @@ class Info(ctypes.Structure):
     ]
 
 
+class Timing(ctypes.Structure):
+    _fields_ = [
+        ("total_ms", ctypes.c_double),
+        ("prep_ms", ctypes.c_double),
+        ("loop_ms", ctypes.c_double),
+        ("loop_active_ms", ctypes.c_double),
+        ("refine_ms", ctypes.c_double),
+        ("final_ms", ctypes.c_double),
+        ("squarings", ctypes.c_int),
+        ("pad", ctypes.c_int),
+        ("square_ms", ctypes.c_float * MAX_LAYERS),
+        ("refine_square_ms", ctypes.c_float * 2),
+    ]
+
+
 _lib = None
 
 
@@ -84,6 +99,8 @@ def lib() -> ctypes.CDLL:
     L.sp2_density.argtypes = [c_void_p, c_int, c_void_p, c_int, c_int, c_int, c_double, ctypes.POINTER(Options),
                               ctypes.POINTER(Info), c_void_p, c_size_t, c_void_p]
     L.sp2_density.restype = c_int
+    L.sp2_density_timed.argtypes = L.sp2_density.argtypes + [ctypes.POINTER(Timing)]
+    L.sp2_density_timed.restype = c_int
     L.sp2_query.argtypes = [c_void_p, c_int, ctypes.POINTER(Options), ctypes.POINTER(Info), c_void_p]
     L.sp2_query.restype = c_int
     L.sp2_square_padded.argtypes = [c_int, c_int, c_int]
@@ -178,9 +195,20 @@ class SP2Error(RuntimeError):
         self.status = status
 
 
+def timing_dict(t: Timing) -> dict:
+    k = int(t.squarings)
+    return {
+        "total_ms": float(t.total_ms), "prep_ms": float(t.prep_ms), "loop_ms": float(t.loop_ms),
+        "loop_active_ms": float(t.loop_active_ms), "refine_ms": float(t.refine_ms),
+        "final_ms": float(t.final_ms), "squarings": k,
+        "square_ms": [float(t.square_ms[i]) for i in range(MAX_LAYERS)],
+        "refine_square_ms": [float(t.refine_square_ms[0]), float(t.refine_square_ms[1])],
+    }
+
+
 def density(h, n_occ: int, tol: float = 0.0, precision="fp16x2", max_layers=100, eps=0.0, bounds=None,
             refine=True, scale_log2=-1, want_energy=False, tile=0, out=None, workspace=None, sync=True,
-            stream=None):
+            stream=None, timed=False):
     """D = theta(mu I - H) with Tr D = n_occ (Alg. 1) for a symmetric FP64 CUDA tensor H.
 
     Returns (D, info) with info a dict (sync=True) or None (sync=False, nothing is
@@ -202,16 +230,21 @@ def density(h, n_occ: int, tol: float = 0.0, precision="fp16x2", max_layers=100,
         workspace = alloc_workspace(need, h.device)
     if out is None:
         out = torch.empty((n, n), dtype=torch.float64, device=h.device)
-    info = Info() if sync else None
-    st = lib().sp2_density(ctypes.c_void_p(h.data_ptr()), h.stride(0), ctypes.c_void_p(out.data_ptr()),
-                           out.stride(0), n, int(n_occ), float(tol), ctypes.byref(opts),
-                           ctypes.byref(info) if info is not None else None,
-                           ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
-                           _stream_ptr(h.device, stream))
+    info = Info() if (sync or timed) else None
+    args = (ctypes.c_void_p(h.data_ptr()), h.stride(0), ctypes.c_void_p(out.data_ptr()), out.stride(0), n,
+            int(n_occ), float(tol), ctypes.byref(opts), ctypes.byref(info) if info is not None else None,
+            ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr(h.device, stream))
+    tm = Timing() if timed else None
+    if timed:
+        st = lib().sp2_density_timed(*args, ctypes.byref(tm))
+    else:
+        st = lib().sp2_density(*args)
     # host-side argument errors leave info untouched (n_padded == 0); the device-side
     # symmetry check also reports EINVAL but fills info and writes D
     if st in (SP2_EDEVICE, SP2_ENOMEM) or (st == SP2_EINVAL and (info is None or int(info.n_padded) == 0)):
         raise SP2Error(st, "sp2_density")
+    if timed:
+        return out, info_dict(info), timing_dict(tm)
     return out, (info_dict(info) if info is not None else None)
 
 
