@@ -71,6 +71,9 @@ typedef struct {
                           FP16X2 and 0 for BF16X2; 0 is the paper's split exactly. */
     int want_energy;   /* nonzero: info->energy = Tr[D H] (the observable of Alg. 1) */
     int tile;          /* output tile edge of the squaring kernels: 0 = automatic, or 64/128/256 */
+    int kernel;        /* split-mode squaring schedule: 0 = automatic, 1 = one workgroup per
+                          tile, 2 = persistent stream-K with 4 wavefronts per workgroup,
+                          3 = persistent stream-K with 8 wavefronts (256 tiles only) */
 } sp2_options;
 
 typedef struct {
@@ -166,14 +169,67 @@ int sp2_query(const void* dWork, int n, const sp2_options* opt, sp2_info* info, 
  * leading dimension ld = n_padded from sp2_square_padded), written to dY with the same
  * layout.  For the split modes the planes of X are formed internally (Eq. Split2) and
  * the square uses Eq. Square.  The output is exactly symmetric.  dWork must hold
- * sp2_square_workspace_size(n, precision, tile) bytes.  Also returns, if trace_frob is
+ * sp2_square_workspace_size(n, precision, tile, kernel) bytes.  Also returns, if trace_frob is
  * non-NULL (host, 2 doubles), Tr Y and ||Y||_F^2 in FP64 (synchronizes).
  */
 int sp2_square_padded(int n, int precision, int tile);
-size_t sp2_square_workspace_size(int n, int precision, int tile);
-int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int scale_log2,
+size_t sp2_square_workspace_size(int n, int precision, int tile, int kernel);
+int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int kernel, int scale_log2,
                float alpha, float beta, float gamma, double* trace_frob, void* dWork,
                size_t work_bytes, void* stream);
+
+/*
+ * sp2_density_batched -- sp2_density for `batch` independent Hamiltonians of (possibly)
+ * different sizes in one go.  All arrays are HOST arrays of length `batch`; dH[i], dD[i]
+ * are device pointers as in sp2_density.  Options apply to every problem (precision
+ * SP2_FP16X2, SP2_BF16X2 or SP2_FP32; caller bounds are not accepted: each problem gets
+ * its own Gershgorin bounds).  Every step of the recursion is one launch covering the
+ * tiles of all problems (each problem keeps its own sigma history and stopping layer);
+ * with use_graph != 0 the whole launch sequence is captured into a hipGraph and
+ * launched once.  The call waits for `stream`, works on a private stream, synchronizes,
+ * and fills infos[i] (host, may be NULL).  Returns SP2_OK or the first non-OK device
+ * status; argument errors return before any work.  dWork: sp2_batched_workspace_size().
+ */
+size_t sp2_batched_workspace_size(int batch, const int* n, const sp2_options* opt);
+int sp2_density_batched(int batch, const double* const* dH, const int* ldh, double* const* dD,
+                        const int* ldd, const int* n, const int* n_occ, double tol,
+                        const sp2_options* opt, sp2_info* infos, int use_graph, void* dWork,
+                        size_t work_bytes, void* stream);
+
+/*
+ * Differentiable generalized-SP2 network (Eq. general SP2 applied to matrices):
+ *
+ *     X_{k+1} = W_k X_k^2 + B_k X_k + c_k I,     k = 0 .. K-1
+ *
+ * with K trainable scalar triples (W_k, B_k, c_k) = (theta_{k,1}, theta_{k,2}, theta_{k,3}).
+ * The SP2 branches are (1, 0, 0) for X^2 and (-1, 2, 0) for 2X - X^2.  X_0 must be
+ * symmetric (e.g. the input layer S_0 of Alg. 1); every X_k then is.
+ *
+ *   precision   SP2_FP16X2 or SP2_BF16X2 (layers as in Alg. 2 with FP32 state) or SP2_FP32.
+ *               The FP16X2 planes hold 2^12 X_k, so |X_k| entries must stay below 16.
+ *   ckpt_every  c >= 1: X_k is kept for k = 0, c, 2c, ... and the backward recomputes the
+ *               layers in between (memory: ceil(K/c) + c + 6 padded matrices); 0 selects
+ *               c = ceil(sqrt(K)).
+ *   dW, dB, dC  device FP32 arrays of K coefficients.
+ *
+ * sp2_net_forward writes X_K (n x n FP32, leading dimension ldk) and keeps the checkpoints
+ * in dWork.  sp2_net_backward takes G_K = dL/dX_K (symmetric, FP32) and the SAME dWork,
+ * n, K, precision and ckpt_every as the preceding forward call, and writes
+ * dL/dW_k = <G_{k+1}, X_k^2>_F, dL/dB_k = <G_{k+1}, X_k>_F, dL/dc_k = Tr G_{k+1} into
+ * ddW, ddB, ddC (device FP32, K each) and, if dG0 != NULL, G_0 = dL/dX_0, where
+ * G_k = W_k (G_{k+1} X_k + X_k G_{k+1}) + B_k G_{k+1}.  The adjoint layers run with FP32
+ * operands on the matrix cores; reductions are FP64.  Both calls enqueue on `stream` and
+ * return without synchronizing; errors are argument errors (SP2_EINVAL, SP2_ENOMEM) or
+ * SP2_EDEVICE.
+ */
+size_t sp2_net_workspace_size(int n, int K, int precision, int ckpt_every);
+int sp2_net_forward(const float* dX0, int ld0, int n, int K, const float* dW, const float* dB,
+                    const float* dC, int precision, int ckpt_every, float* dXK, int ldk,
+                    void* dWork, size_t work_bytes, void* stream);
+int sp2_net_backward(const float* dGK, int ldg, int n, int K, const float* dW, const float* dB,
+                     const float* dC, int precision, int ckpt_every, float* dG0, int ldg0,
+                     float* ddW, float* ddB, float* ddC, void* dWork, size_t work_bytes,
+                     void* stream);
 
 #ifdef __cplusplus
 }

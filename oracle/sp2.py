@@ -129,6 +129,18 @@ def mixed_square(x: np.ndarray, fmt: str = "fp16", scale_log2: int = 0) -> np.nd
     return (a + (b + b.T)) * (2.0 ** (-2 * scale_log2))
 
 
+def mixed_square_rows(x: np.ndarray, rows, fmt: str = "fp16", scale_log2: int = 0) -> np.ndarray:
+    """Selected rows of mixed_square (same definition, evaluated row by row for large X)."""
+    x0, x1 = split_planes(x, fmt, scale_log2)
+    x0 = x0.astype(np.float64)
+    x1 = x1.astype(np.float64)
+    r = np.asarray(rows)
+    a = x0[r] @ x0
+    b = x0[r] @ x1          # rows of X0 X1
+    bt = x1[r] @ x0         # rows of X1 X0 = (X0 X1)^T for symmetric X
+    return (a + (b + bt)) * (2.0 ** (-2 * scale_log2))
+
+
 def mixed_square_fp32(fmt: str = "fp16", scale_log2: int = 0) -> Callable:
     """Activation returning FP32[mixed_square(X)] (the single-precision layer state)."""
     def f(x):

@@ -98,10 +98,10 @@ __global__ void k_state_init(DevState* st, StateParams p) {
 // [H_ii - r_i, H_ii + r_i] widened by (2n + 4) ulp-units for the summation error.
 constexpr int kGershRowsPerBlock = kThreads / 64;
 
-__global__ __launch_bounds__(kThreads) void k_gershgorin(const double* __restrict__ h, int ldh, int n,
-                                                         double* __restrict__ blk) {
+__device__ __forceinline__ void gershgorin_body(const double* __restrict__ h, int ldh, int n,
+                                                         double* __restrict__ blk, int bid) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int row = blockIdx.x * kGershRowsPerBlock + wave;
+    const int row = bid * kGershRowsPerBlock + wave;
     __shared__ double sh[3][kGershRowsPerBlock];
     double lo = INFINITY, hi = -INFINITY, bad = 0.0;
     if (row < n) {
@@ -128,13 +128,13 @@ __global__ __launch_bounds__(kThreads) void k_gershgorin(const double* __restric
             hi = fmax(hi, sh[1][w]);
             bad = fmax(bad, sh[2][w]);
         }
-        blk[3 * blockIdx.x + 0] = lo;
-        blk[3 * blockIdx.x + 1] = hi;
-        blk[3 * blockIdx.x + 2] = bad;
+        blk[3 * bid + 0] = lo;
+        blk[3 * bid + 1] = hi;
+        blk[3 * bid + 2] = bad;
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_bounds(DevState* st, const double* __restrict__ blk, int nblk) {
+__device__ __forceinline__ void bounds_body(DevState* st, const double* __restrict__ blk, int nblk) {
     __shared__ double sh[3][kThreads];
     const int t = threadIdx.x;
     double lo = INFINITY, hi = -INFINITY, bad = 0.0;
@@ -177,17 +177,17 @@ __global__ __launch_bounds__(kThreads) void k_bounds(DevState* st, const double*
 constexpr int kInitTile = 64;
 
 template <typename St, typename T16, bool kSplit>
-__global__ __launch_bounds__(kThreads) void k_init(const double* __restrict__ h, int ldh,
+__device__ __forceinline__ void init_body(const double* __restrict__ h, int ldh,
                                                    const DevState* __restrict__ st, St* __restrict__ s_out,
                                                    T16* __restrict__ p0, T16* __restrict__ p1, float in_scale,
-                                                   double* __restrict__ parts) {
+                                                   double* __restrict__ parts, int bid) {
     __shared__ double a[kInitTile][kInitTile + 1];
     __shared__ double b[kInitTile][kInitTile + 1];
     __shared__ double red[3][kThreads];
     const int n = st->n, np = st->n_padded;
     const int T = np / kInitTile;
     int I, J;
-    tile_of(blockIdx.x, T, T, &I, &J);   // plain column-strip order
+    tile_of(bid, T, T, &I, &J);   // plain column-strip order
     const int t = threadIdx.x;
     const int r0 = I * kInitTile, c0 = J * kInitTile;
     for (int idx = t; idx < kInitTile * kInitTile; idx += kThreads) {
@@ -255,9 +255,9 @@ __global__ __launch_bounds__(kThreads) void k_init(const double* __restrict__ h,
         __syncthreads();
     }
     if (t == 0) {
-        parts[3 * blockIdx.x + 0] = v2[0];
-        parts[3 * blockIdx.x + 1] = v2[1];
-        parts[3 * blockIdx.x + 2] = red[2][0];
+        parts[3 * bid + 0] = v2[0];
+        parts[3 * bid + 1] = v2[1];
+        parts[3 * bid + 2] = red[2][0];
     }
 }
 
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kThreads) void k_init(const double* __restrict__ h,
 // so IdErr_n = Tr[S_{n-1} - S_{n-1}^2] is known before X_n is formed, and layer n's
 // kernels receive sigma_n as coefficients (or a skip flag once a test has held).
 // ---------------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_control(DevState* st, const double* __restrict__ parts,
+__device__ __forceinline__ void control_body(DevState* st, const double* __restrict__ parts,
                                                       int nparts, int stride, int layer,
                                                       volatile int* __restrict__ host_flag) {
     __shared__ double sh[2 * kThreads];
@@ -338,13 +338,13 @@ __global__ __launch_bounds__(kThreads) void k_control(DevState* st, const double
 }
 
 template <typename Src>
-__global__ __launch_bounds__(kThreads) void k_select_f64(const DevState* __restrict__ st, const Src* __restrict__ s0,
+__device__ __forceinline__ void select_body(const DevState* __restrict__ st, const Src* __restrict__ s0,
                                                          const Src* __restrict__ s1, double* __restrict__ out,
-                                                         int ld_out, int n_valid, int np) {
+                                                         int ld_out, int n_valid, int np, int bid, int nbid) {
     const Src* src = st->refine_src ? s1 : s0;
     const size_t total = (size_t)n_valid * n_valid;
-    for (size_t idx = (size_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
-         idx += (size_t)gridDim.x * kThreads) {
+    for (size_t idx = (size_t)bid * kThreads + threadIdx.x; idx < total;
+         idx += (size_t)nbid * kThreads) {
         const int i = (int)(idx / n_valid), j = (int)(idx % n_valid);
         out[(size_t)i * ld_out + j] = (double)src[(size_t)i * np + j];
     }
@@ -353,14 +353,14 @@ __global__ __launch_bounds__(kThreads) void k_select_f64(const DevState* __restr
 // Rows per block of the final reductions.
 constexpr int kStatRows = 4;
 
-__global__ __launch_bounds__(kThreads) void k_dstats(const double* __restrict__ d, int ldd,
+__device__ __forceinline__ void dstats_body(const double* __restrict__ d, int ldd,
                                                      const double* __restrict__ h, int ldh, int n,
-                                                     double* __restrict__ parts) {
+                                                     double* __restrict__ parts, int bid) {
     __shared__ double sh[3 * kThreads];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double v[3] = {0.0, 0.0, 0.0};
     for (int rr = wave; rr < kStatRows; rr += kThreads / 64) {
-        const int i = blockIdx.x * kStatRows + rr;
+        const int i = bid * kStatRows + rr;
         if (i >= n) break;
         const double* dr = d + (size_t)i * ldd;
         const double* hr = h ? h + (size_t)i * ldh : nullptr;
@@ -373,13 +373,13 @@ __global__ __launch_bounds__(kThreads) void k_dstats(const double* __restrict__ 
     }
     block_sum<3>(v, sh);
     if (threadIdx.x == 0) {
-        parts[3 * blockIdx.x + 0] = v[0];
-        parts[3 * blockIdx.x + 1] = v[1];
-        parts[3 * blockIdx.x + 2] = v[2];
+        parts[3 * bid + 0] = v[0];
+        parts[3 * bid + 1] = v[1];
+        parts[3 * bid + 2] = v[2];
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_finalize(DevState* st, const double* __restrict__ dparts, int nd,
+__device__ __forceinline__ void finalize_body(DevState* st, const double* __restrict__ dparts, int nd,
                                                        const double* __restrict__ iparts, int ni) {
     __shared__ double sh[3 * kThreads];
     __shared__ double mx[kThreads];
@@ -459,6 +459,10 @@ __global__ void k_set3(float* dst, float a, float b, float c) {
     }
 }
 
+__global__ void k_zero_ints(int* p, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
 // Occupation 0 or n: no recursion is run; the state records a converged call of 0 layers.
 __global__ void k_mark_trivial(DevState* st) {
     if (threadIdx.x == 0) {
@@ -467,6 +471,84 @@ __global__ void k_mark_trivial(DevState* st) {
         st->layers = 0;
         st->skip = 1;
     }
+}
+
+__global__ __launch_bounds__(kThreads) void k_gershgorin(const double* __restrict__ h, int ldh, int n,
+                                                         double* __restrict__ blk) {
+    gershgorin_body(h, ldh, n, blk, blockIdx.x);
+}
+__global__ __launch_bounds__(kThreads) void k_bounds(DevState* st, const double* __restrict__ blk, int nblk) {
+    bounds_body(st, blk, nblk);
+}
+__global__ __launch_bounds__(kThreads) void k_control(DevState* st, const double* __restrict__ parts, int nparts,
+                                                      int stride, int layer, volatile int* __restrict__ host_flag) {
+    control_body(st, parts, nparts, stride, layer, host_flag);
+}
+__global__ __launch_bounds__(kThreads) void k_finalize(DevState* st, const double* __restrict__ dparts, int nd,
+                                                       const double* __restrict__ iparts, int ni) {
+    finalize_body(st, dparts, nd, iparts, ni);
+}
+template <typename St, typename T16, bool kSplit>
+__global__ __launch_bounds__(kThreads) void k_init(const double* __restrict__ h, int ldh,
+                                                   const DevState* __restrict__ st, St* __restrict__ s_out,
+                                                   T16* __restrict__ p0, T16* __restrict__ p1, float in_scale,
+                                                   double* __restrict__ parts) {
+    init_body<St, T16, kSplit>(h, ldh, st, s_out, p0, p1, in_scale, parts, blockIdx.x);
+}
+template <typename Src>
+__global__ __launch_bounds__(kThreads) void k_select_f64(const DevState* __restrict__ st, const Src* __restrict__ s0,
+                                                         const Src* __restrict__ s1, double* __restrict__ out,
+                                                         int ld_out, int n_valid, int np) {
+    select_body<Src>(st, s0, s1, out, ld_out, n_valid, np, blockIdx.x, gridDim.x);
+}
+__global__ __launch_bounds__(kThreads) void k_dstats(const double* __restrict__ d, int ldd,
+                                                     const double* __restrict__ h, int ldh, int n,
+                                                     double* __restrict__ parts) {
+    dstats_body(d, ldd, h, ldh, n, parts, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------------
+// Batched versions: one launch covers all problems; blocks are split between problems
+// by the prefix offsets `offs`, single-block steps use one block per problem.
+// ---------------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_gershgorin_g(const BatchProblem* __restrict__ pr,
+                                                           const int* __restrict__ offs, int np_) {
+    const int p = find_group(offs, np_, blockIdx.x);
+    gershgorin_body(pr[p].h, pr[p].ldh, pr[p].n, pr[p].gersh, blockIdx.x - offs[p]);
+}
+__global__ __launch_bounds__(kThreads) void k_bounds_g(const BatchProblem* __restrict__ pr) {
+    const BatchProblem& q = pr[blockIdx.x];
+    if (q.st->have_bounds) return;
+    bounds_body(q.st, q.gersh, q.gersh_blocks);
+}
+template <typename T16, bool kSplit>
+__global__ __launch_bounds__(kThreads) void k_init_g(const BatchProblem* __restrict__ pr,
+                                                     const int* __restrict__ offs, int np_) {
+    const int p = find_group(offs, np_, blockIdx.x);
+    const BatchProblem& q = pr[p];
+    init_body<float, T16, kSplit>(q.h, q.ldh, q.st, (float*)q.s[0], (T16*)q.pl[0][0], (T16*)q.pl[0][1],
+                                  q.in_scale, q.init_parts, blockIdx.x - offs[p]);
+}
+__global__ __launch_bounds__(kThreads) void k_control_g(const BatchProblem* __restrict__ pr, int layer) {
+    const BatchProblem& q = pr[blockIdx.x];
+    if (layer == 1) control_body(q.st, q.init_parts, q.init_tiles, 3, layer, nullptr);
+    else control_body(q.st, q.main_parts, q.main_tiles, 2, layer, nullptr);
+}
+__global__ __launch_bounds__(kThreads) void k_select_g(const BatchProblem* __restrict__ pr, int per_problem) {
+    const int p = blockIdx.x / per_problem;
+    const BatchProblem& q = pr[p];
+    select_body<float>(q.st, (const float*)q.s[0], (const float*)q.s[1], q.s64, q.np, q.np, q.np,
+                       blockIdx.x - p * per_problem, per_problem);
+}
+__global__ __launch_bounds__(kThreads) void k_dstats_g(const BatchProblem* __restrict__ pr,
+                                                       const int* __restrict__ offs, int np_) {
+    const int p = find_group(offs, np_, blockIdx.x);
+    const BatchProblem& q = pr[p];
+    dstats_body(q.d, q.ldd, q.want_energy ? q.h : nullptr, q.ldh, q.n, q.dstats, blockIdx.x - offs[p]);
+}
+__global__ __launch_bounds__(kThreads) void k_finalize_g(const BatchProblem* __restrict__ pr) {
+    const BatchProblem& q = pr[blockIdx.x];
+    finalize_body(q.st, q.dstats, q.dstats_blocks, q.init_parts, q.init_tiles);
 }
 
 inline int grid_for(size_t total) {
@@ -609,8 +691,51 @@ hipError_t launch_set3(float* dst, float a, float b, float c, hipStream_t s) {
     hipLaunchKernelGGL(k_set3, dim3(1), dim3(64), 0, s, dst, a, b, c);
     return hipGetLastError();
 }
+hipError_t launch_zero_ints(int* p, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_ints, dim3(4), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
 hipError_t launch_mark_trivial(DevState* st, hipStream_t s) {
     hipLaunchKernelGGL(k_mark_trivial, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
+}
+}  // namespace sp2
+
+namespace sp2 {
+hipError_t launch_batch_gershgorin(const BatchProblem* pr, const int* offs, int nprob, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_gershgorin_g, dim3(blocks), dim3(kThreads), 0, s, pr, offs, nprob);
+    return hipGetLastError();
+}
+hipError_t launch_batch_bounds(const BatchProblem* pr, int nprob, hipStream_t s) {
+    hipLaunchKernelGGL(k_bounds_g, dim3(nprob), dim3(kThreads), 0, s, pr);
+    return hipGetLastError();
+}
+hipError_t launch_batch_init(int precision, const BatchProblem* pr, const int* offs, int nprob, int blocks,
+                             hipStream_t s) {
+    if (precision == SP2_FP16X2)
+        hipLaunchKernelGGL((k_init_g<_Float16, true>), dim3(blocks), dim3(kThreads), 0, s, pr, offs, nprob);
+    else if (precision == SP2_BF16X2)
+        hipLaunchKernelGGL((k_init_g<__bf16, true>), dim3(blocks), dim3(kThreads), 0, s, pr, offs, nprob);
+    else if (precision == SP2_FP32)
+        hipLaunchKernelGGL((k_init_g<_Float16, false>), dim3(blocks), dim3(kThreads), 0, s, pr, offs, nprob);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+hipError_t launch_batch_control(const BatchProblem* pr, int nprob, int layer, hipStream_t s) {
+    hipLaunchKernelGGL(k_control_g, dim3(nprob), dim3(kThreads), 0, s, pr, layer);
+    return hipGetLastError();
+}
+hipError_t launch_batch_select(const BatchProblem* pr, int nprob, int per_problem, hipStream_t s) {
+    hipLaunchKernelGGL(k_select_g, dim3(nprob * per_problem), dim3(kThreads), 0, s, pr, per_problem);
+    return hipGetLastError();
+}
+hipError_t launch_batch_dstats(const BatchProblem* pr, const int* offs, int nprob, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_dstats_g, dim3(blocks), dim3(kThreads), 0, s, pr, offs, nprob);
+    return hipGetLastError();
+}
+hipError_t launch_batch_finalize(const BatchProblem* pr, int nprob, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_g, dim3(nprob), dim3(kThreads), 0, s, pr);
     return hipGetLastError();
 }
 }  // namespace sp2

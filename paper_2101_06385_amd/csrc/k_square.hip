@@ -93,10 +93,10 @@ __device__ inline void tile_partials(double tr, double fr, double* scratch, doub
 constexpr int kBK = 32;                 // halves per row per stage (64 bytes)
 constexpr int kRowBytes = kBK * 2;
 
-__device__ inline int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+__device__ inline int swz(int r) { return (r >> 2) & 3; }
 
 template <typename T16, int BT, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN) void k_square_split(SquareArgs a) {
+__device__ __forceinline__ void split_body(const SquareArgs& a, int t) {
     constexpr int NT = 64 * WM * WN;
     constexpr int WTM = BT / WM, WTN = BT / WN;
     constexpr int MB = WTM / 32, NB = WTN / 32;
@@ -110,9 +110,6 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_split(SquareArgs a) {
 
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
 
-    if (a.skip && *a.skip) return;
-    const int t = xcd_tile_index(blockIdx.x, a.per, a.ntiles);
-    if (t < 0) return;
     int I, J;
     tile_of(t, a.T, 8, &I, &J);
     const int np = a.np;
@@ -335,7 +332,7 @@ struct PlainOps<float> {
 };
 
 template <typename E, int BT, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN) void k_square_plain(SquareArgs a) {
+__device__ __forceinline__ void plain_body(const SquareArgs& a, int t) {
     typedef PlainOps<E> Ops;
     constexpr int NT = 64 * WM * WN;
     constexpr int WTM = BT / WM, WTN = BT / WN;
@@ -352,9 +349,6 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_plain(SquareArgs a) {
     __shared__ E lds[2 * 2 * ARR];
     __shared__ double red[2 * (NT / 64)];
 
-    if (a.skip && *a.skip) return;
-    const int t = xcd_tile_index(blockIdx.x, a.per, a.ntiles);
-    if (t < 0) return;
     int I, J;
     tile_of(t, a.T, 8, &I, &J);
     const int np = a.np;
@@ -459,6 +453,42 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_plain(SquareArgs a) {
     if (a.parts) tile_partials<NT / 64>(tr, fr, red, a.parts + 2 * t);
 }
 
+// Single problem: hardware block -> XCD-grouped tile index.
+template <typename T16, int BT, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void k_square_split(SquareArgs a) {
+    if (a.skip && *a.skip) return;
+    const int t = xcd_tile_index(blockIdx.x, a.per, a.ntiles);
+    if (t < 0) return;
+    split_body<T16, BT, WM, WN>(a, t);
+}
+template <typename E, int BT, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void k_square_plain(SquareArgs a) {
+    if (a.skip && *a.skip) return;
+    const int t = xcd_tile_index(blockIdx.x, a.per, a.ntiles);
+    if (t < 0) return;
+    plain_body<E, BT, WM, WN>(a, t);
+}
+
+// Many problems in one launch: block b belongs to the problem p with offs[p] <= b <
+// offs[p + 1] and handles that problem's tile b - offs[p]; each problem brings its own
+// arguments (buffers, coefficients, skip flag).
+template <typename T16, int BT, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void k_square_split_g(const SquareArgs* __restrict__ descs,
+                                                                 const int* __restrict__ offs, int nprob) {
+    const int p = find_group(offs, nprob, blockIdx.x);
+    const SquareArgs a = descs[p];
+    if (a.skip && *a.skip) return;
+    split_body<T16, BT, WM, WN>(a, blockIdx.x - offs[p]);
+}
+template <typename E, int BT, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void k_square_plain_g(const SquareArgs* __restrict__ descs,
+                                                                 const int* __restrict__ offs, int nprob) {
+    const int p = find_group(offs, nprob, blockIdx.x);
+    const SquareArgs a = descs[p];
+    if (a.skip && *a.skip) return;
+    plain_body<E, BT, WM, WN>(a, blockIdx.x - offs[p]);
+}
+
 template <int BT>
 int grid_of(int np, int* T, int* ntiles, int* per) {
     *T = np / BT;
@@ -491,6 +521,40 @@ hipError_t launch_square_split(int precision, int tile, const SquareArgs& a, hip
         if (tile == 256) SP2_L(__bf16, 256, 2, 4);
         else if (tile == 128) SP2_L(__bf16, 128, 2, 2);
         else SP2_L(__bf16, 64, 2, 2);
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef SP2_L
+    return hipGetLastError();
+}
+
+hipError_t launch_square_split_g(int precision, int tile, const SquareArgs* descs, const int* offs, int nprob,
+                                 int blocks, hipStream_t s) {
+#define SP2_L(T16, BT, WM, WN) \
+    hipLaunchKernelGGL((k_square_split_g<T16, BT, WM, WN>), dim3(blocks), dim3(64 * WM * WN), 0, s, descs, offs, nprob)
+    if (precision == SP2_FP16X2) {
+        if (tile == 128) SP2_L(_Float16, 128, 2, 2);
+        else SP2_L(_Float16, 64, 2, 2);
+    } else if (precision == SP2_BF16X2) {
+        if (tile == 128) SP2_L(__bf16, 128, 2, 2);
+        else SP2_L(__bf16, 64, 2, 2);
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef SP2_L
+    return hipGetLastError();
+}
+
+hipError_t launch_square_plain_g(int precision, int tile, const SquareArgs* descs, const int* offs, int nprob,
+                                 int blocks, hipStream_t s) {
+#define SP2_L(E, BT, WM, WN) \
+    hipLaunchKernelGGL((k_square_plain_g<E, BT, WM, WN>), dim3(blocks), dim3(64 * WM * WN), 0, s, descs, offs, nprob)
+    if (precision == SP2_FP64) {
+        if (tile == 128) SP2_L(double, 128, 2, 2);
+        else SP2_L(double, 64, 2, 2);
+    } else if (precision == SP2_FP32) {
+        if (tile == 128) SP2_L(float, 128, 2, 2);
+        else SP2_L(float, 64, 2, 2);
     } else {
         return hipErrorInvalidValue;
     }

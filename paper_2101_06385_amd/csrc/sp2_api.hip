@@ -8,6 +8,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <vector>
+
 using namespace sp2;
 
 namespace {
@@ -18,7 +20,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 struct Opts {
-    int precision, max_layers, have_bounds, refine, scale_log2, want_energy, tile;
+    int precision, max_layers, have_bounds, refine, scale_log2, want_energy, tile, kernel;
     double eps, emin, emax;
 };
 
@@ -32,6 +34,7 @@ bool read_opts(const sp2_options* o, Opts* r) {
     r->refine = o->refine;
     r->want_energy = o->want_energy;
     r->tile = o->tile;
+    r->kernel = o->kernel;
     r->eps = o->eps;
     r->emin = o->emin;
     r->emax = o->emax;
@@ -43,6 +46,8 @@ bool read_opts(const sp2_options* o, Opts* r) {
     if (r->max_layers < 1 || r->max_layers >= SP2_MAX_LAYERS) return false;
     if (r->tile != 0 && r->tile != 64 && r->tile != 128 && r->tile != 256) return false;
     if (r->tile == 256 && !split) return false;
+    if (r->kernel < 0 || r->kernel > 3) return false;
+    if (r->kernel == 3 && r->tile != 0 && r->tile != 256) return false;
     if (!isfinite(r->eps)) return false;
     if (r->have_bounds && !(isfinite(r->emin) && isfinite(r->emax) && r->emax > r->emin)) return false;
     return true;
@@ -52,11 +57,37 @@ struct Plan {
     int n, np, precision, tile_main, tile_ref, scale_log2;
     bool split;
     int init_tiles, main_T, main_tiles, main_per, ref_T, ref_tiles, ref_per, gersh_blocks, dstats_blocks;
-    size_t off_init_parts, off_main_parts, off_gersh, off_dstats, off_s[2], off_p[2][2], off_s64, off_y, total;
+    int kernel;       // resolved request: 1 = one workgroup per tile, 2/3 = stream-K (4/8 waves)
+    bool sk_capable;  // stream-K buffers are part of the workspace
+    size_t off_init_parts, off_main_parts, off_gersh, off_dstats, off_s[2], off_p[2][2], off_s64, off_y;
+    size_t off_sk_partial, off_sk_counter, total;
 };
 
+// Stream-K needs a tile of 128 or 256 in a split mode; kernel 1 asks for the
+// one-workgroup-per-tile schedule.  The automatic choice takes stream-K for 256 tiles
+// only: with 128 tiles two one-tile workgroups per CU measured faster than stream-K.
+bool sk_wanted(bool split, int tile, int kernel) {
+    if (!split || tile < 128 || kernel == 1) return false;
+    return kernel != 0 || tile == 256;
+}
+
+// Resolves the squaring schedule for this device; false = one workgroup per tile.
+bool sk_resolve(const Plan& p, StreamK* sk, int* waves) {
+    if (!p.sk_capable) return false;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+    int per_cu = 0, T = 0, nt = 0;
+    const int tile_for_plan = p.tile_main;
+    if (!square_sk_plan(tile_for_plan, p.np, cus, &per_cu, sk, &T, &nt)) return false;
+    *waves = (p.kernel == 3 && p.tile_main == 256) ? 8 : 4;
+    return true;
+}
+
 int auto_tile_main(int n, bool split) {
-    if (split) return n <= 256 ? 64 : (n <= 2048 ? 128 : 256);
+    // split modes: 256 tiles once there are enough of them for every CU (stream-K needs
+    // at least one tile per workgroup), 128 below that
+    if (split) return n <= 256 ? 64 : (n < 6144 ? 128 : 256);
     return n <= 512 ? 64 : 128;
 }
 
@@ -101,6 +132,12 @@ void make_plan(int n, const Opts& o, Plan* p) {
     off = align_up(off + (o.refine ? 8 * np2 : 0));
     p->off_y = off;
     off = align_up(off + (o.refine ? 8 * np2 : 0));
+    p->kernel = o.kernel;
+    p->sk_capable = sk_wanted(p->split, p->tile_main, o.kernel);
+    p->off_sk_partial = off;
+    if (p->sk_capable) off = align_up(off + square_sk_partial_bytes(p->tile_main, p->np));
+    p->off_sk_counter = off;
+    if (p->sk_capable) off = align_up(off + sizeof(int) * kMaxSkGrid);
     p->total = off;
 }
 
@@ -314,6 +351,15 @@ static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, in
         SP2_TRY(launch_init_np(dH, ldh, st, p.np, o.precision, S[0], P[0][0], P[0][1], p.scale_log2, init_parts, s));
         SP2_TRY(ev.rec(ev.prep, s));
 
+        StreamK sk;
+        memset(&sk, 0, sizeof(sk));
+        int sk_waves = 4;
+        const bool use_sk = sk_resolve(p, &sk, &sk_waves);
+        if (use_sk) {
+            sk.partial = (float*)(ws + p.off_sk_partial);
+            sk.counter = (int*)(ws + p.off_sk_counter);
+            SP2_TRY(launch_zero_ints(sk.counter, kMaxSkGrid, s));
+        }
         SquareArgs a;
         memset(&a, 0, sizeof(a));
         a.parts = main_parts;
@@ -362,7 +408,9 @@ static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, in
             a.p1_out = P[out][1];
             ev.launched = layer;
             SP2_TRY(ev.rec(ev.sq_b[layer], s));
-            if (p.split)
+            if (use_sk)
+                SP2_TRY(launch_square_sk(o.precision, p.tile_main, sk_waves, a, sk, s));
+            else if (p.split)
                 SP2_TRY(launch_square_split(o.precision, p.tile_main, a, s));
             else
                 SP2_TRY(launch_square_plain(o.precision, p.tile_main, a, s));
@@ -454,7 +502,7 @@ int sp2_square_padded(int n, int precision, int tile) {
     return round_up(n, t);
 }
 
-size_t sp2_square_workspace_size(int n, int precision, int tile) {
+size_t sp2_square_workspace_size(int n, int precision, int tile, int kernel) {
     const int np = sp2_square_padded(n, precision, tile);
     if (np <= 0) return 0;
     const bool split = precision == SP2_FP16X2 || precision == SP2_BF16X2;
@@ -466,22 +514,27 @@ size_t sp2_square_workspace_size(int n, int precision, int tile) {
     off = align_up(off + sizeof(double) * 2 * nt);     // partials
     off = align_up(off + sizeof(double) * 2);          // sums
     if (split) off = align_up(off + 4 * (size_t)np * np);
+    if (sk_wanted(split, t, kernel)) {
+        off = align_up(off + square_sk_partial_bytes(t, np));
+        off = align_up(off + sizeof(int) * kMaxSkGrid);
+    }
     return off;
 }
 
-int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int scale_log2, float alpha, float beta,
-               float gamma, double* trace_frob, void* dWork, size_t work_bytes, void* stream) {
+int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int kernel, int scale_log2, float alpha,
+               float beta, float gamma, double* trace_frob, void* dWork, size_t work_bytes, void* stream) {
     if (!dX || !dY || !dWork || n <= 0) return SP2_EINVAL;
     if (precision < SP2_FP64 || precision > SP2_BF16X2) return SP2_EINVAL;
     const bool split = precision == SP2_FP16X2 || precision == SP2_BF16X2;
     if (tile != 0 && tile != 64 && tile != 128 && !(tile == 256 && split)) return SP2_EINVAL;
+    if (kernel < 0 || kernel > 3) return SP2_EINVAL;
     if (scale_log2 < 0) scale_log2 = precision == SP2_FP16X2 ? 12 : 0;
     if (!split) scale_log2 = 0;
     if (scale_log2 > (precision == SP2_FP16X2 ? 14 : 60)) return SP2_EINVAL;
     if (((uintptr_t)dWork) % kAlign) return SP2_EINVAL;
     const int t = tile ? tile : auto_tile_main(n, split);
     const int np = round_up(n, t);
-    if (work_bytes < sp2_square_workspace_size(n, precision, tile)) return SP2_ENOMEM;
+    if (work_bytes < sp2_square_workspace_size(n, precision, tile, kernel)) return SP2_ENOMEM;
     hipStream_t s = (hipStream_t)stream;
     char* ws = (char*)dWork;
     int T, nt, per;
@@ -511,10 +564,28 @@ int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int sca
     if (split) {
         void* p0 = ws + off;
         void* p1 = ws + off + 2 * (size_t)np * np;
+        off = align_up(off + 4 * (size_t)np * np);
         SP2_TRY(launch_split((const float*)dX, p0, p1, np, precision, scale_log2, s));
         a.x0 = p0;
         a.x1 = p1;
-        SP2_TRY(launch_square_split(precision, t, a, s));
+        Plan pl;
+        memset(&pl, 0, sizeof(pl));
+        pl.np = np;
+        pl.tile_main = t;
+        pl.kernel = kernel;
+        pl.sk_capable = sk_wanted(true, t, kernel);
+        StreamK sk;
+        memset(&sk, 0, sizeof(sk));
+        int waves = 4;
+        if (sk_resolve(pl, &sk, &waves)) {
+            sk.partial = (float*)(ws + off);
+            off = align_up(off + square_sk_partial_bytes(t, np));
+            sk.counter = (int*)(ws + off);
+            SP2_TRY(launch_zero_ints(sk.counter, kMaxSkGrid, s));
+            SP2_TRY(launch_square_sk(precision, t, waves, a, sk, s));
+        } else {
+            SP2_TRY(launch_square_split(precision, t, a, s));
+        }
     } else {
         a.x0 = dX;
         SP2_TRY(launch_square_plain(precision, t, a, s));
@@ -525,6 +596,281 @@ int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int sca
         SP2_TRY(hipMemcpy(trace_frob, sums, 2 * sizeof(double), hipMemcpyDeviceToHost));
     }
     return SP2_OK;
+}
+
+// =====================================================================================
+// Batched solve: many independent Hamiltonians of different sizes.  Every step of the
+// single-problem sequence becomes one launch covering all problems (grouped kernels: the
+// blocks of a launch are split between problems by prefix offsets), and the whole
+// sequence is captured once into a hipGraph that is launched as one unit.
+// =====================================================================================
+namespace {
+
+struct BatchLayout {
+    int batch, tile, ref_tile;
+    std::vector<int> nontrivial;        // indices of problems that run the recursion
+    std::vector<Plan> plans;
+    std::vector<size_t> region;         // byte offset of each problem's region
+    size_t off_probs, off_sq, off_offs, off_states, total;
+    int n_offs;                         // entries per offset array (nontrivial + 1)
+};
+
+bool batch_layout(int batch, const int* n, const int* n_occ, const Opts& o, BatchLayout* L) {
+    L->batch = batch;
+    int nmin = 1 << 30;
+    for (int i = 0; i < batch; ++i) nmin = n[i] < nmin ? n[i] : nmin;
+    L->tile = o.tile ? o.tile : (nmin <= 256 ? 64 : 128);
+    if (L->tile == 256) L->tile = 128;
+    L->plans.resize(batch);
+    L->region.resize(batch);
+    L->nontrivial.clear();
+    for (int i = 0; i < batch; ++i) {
+        Opts oi = o;
+        oi.tile = L->tile;
+        oi.kernel = 1;   // one workgroup per tile: grouped launches
+        make_plan(n[i], oi, &L->plans[i]);
+        if (n_occ && n_occ[i] > 0 && n_occ[i] < n[i]) L->nontrivial.push_back(i);
+    }
+    const int nt = (int)L->nontrivial.size();
+    L->n_offs = nt + 1;
+    size_t off = 0;
+    L->off_probs = off;
+    off = align_up(off + sizeof(BatchProblem) * (nt ? nt : 1));
+    L->off_sq = off;
+    off = align_up(off + sizeof(SquareArgs) * 4 * (nt ? nt : 1));   // even layer, odd layer, refine 1, refine 2
+    L->off_offs = off;
+    off = align_up(off + sizeof(int) * 5 * L->n_offs);               // gersh, init, main, ref, dstats
+    L->off_states = off;   // (unused: each problem's state sits at the start of its region)
+    for (int i = 0; i < batch; ++i) {
+        L->region[i] = off;
+        off = align_up(off + L->plans[i].total);
+    }
+    L->total = off;
+    return true;
+}
+
+bool batch_opts(const sp2_options* opt, Opts* o) {
+    if (!read_opts(opt, o)) return false;
+    if (o->precision == SP2_FP64) return false;   // the batched path keeps FP32 state
+    if (o->have_bounds) return false;             // per-problem Gershgorin bounds only
+    return true;
+}
+
+}  // namespace
+
+size_t sp2_batched_workspace_size(int batch, const int* n, const sp2_options* opt) {
+    if (batch <= 0 || !n) return 0;
+    Opts o;
+    if (!batch_opts(opt, &o)) return 0;
+    for (int i = 0; i < batch; ++i)
+        if (n[i] <= 0 || n[i] > 65536) return 0;
+    BatchLayout L;
+    batch_layout(batch, n, nullptr, o, &L);
+    return L.total;
+}
+
+int sp2_density_batched(int batch, const double* const* dH, const int* ldh, double* const* dD, const int* ldd,
+                        const int* n, const int* n_occ, double tol, const sp2_options* opt, sp2_info* infos,
+                        int use_graph, void* dWork, size_t work_bytes, void* stream) {
+    Opts o;
+    if (batch <= 0 || !dH || !ldh || !dD || !ldd || !n || !n_occ || !dWork || !batch_opts(opt, &o)) return SP2_EINVAL;
+    if (((uintptr_t)dWork) % kAlign) return SP2_EINVAL;
+    for (int i = 0; i < batch; ++i)
+        if (!dH[i] || !dD[i] || n[i] <= 0 || n[i] > 65536 || ldh[i] < n[i] || ldd[i] < n[i] || n_occ[i] < 0 ||
+            n_occ[i] > n[i])
+            return SP2_EINVAL;
+    BatchLayout L;
+    batch_layout(batch, n, n_occ, o, &L);
+    if (work_bytes < L.total) return SP2_ENOMEM;
+    char* ws = (char*)dWork;
+    hipStream_t user = (hipStream_t)stream;
+    sp2_options opt1;
+    if (opt) opt1 = *opt;
+    else sp2_default_options(&opt1);
+    opt1.tile = L.tile;
+    opt1.kernel = 1;
+
+    // problems with an empty or full occupation: D = 0 or I, through the single path
+    for (int i = 0; i < batch; ++i) {
+        if (n_occ[i] > 0 && n_occ[i] < n[i]) continue;
+        const int st = sp2_density(dH[i], ldh[i], dD[i], ldd[i], n[i], n_occ[i], tol, &opt1, nullptr,
+                                   ws + L.region[i], L.plans[i].total, stream);
+        if (st != SP2_OK) return st;
+    }
+    const int nt = (int)L.nontrivial.size();
+    if (nt > 0) {
+        // ---------------------------------------------------------------- descriptors
+        std::vector<BatchProblem> probs(nt);
+        std::vector<SquareArgs> sq(4 * nt);
+        std::vector<int> offs(5 * L.n_offs, 0);
+        std::vector<DevState> states(nt);
+        int* o_g = offs.data();
+        int* o_i = o_g + L.n_offs;
+        int* o_m = o_i + L.n_offs;
+        int* o_r = o_m + L.n_offs;
+        int* o_d = o_r + L.n_offs;
+        BatchProblem* d_probs = (BatchProblem*)(ws + L.off_probs);
+        for (int k = 0; k < nt; ++k) {
+            const int i = L.nontrivial[k];
+            const Plan& p = L.plans[i];
+            char* r = ws + L.region[i];
+            BatchProblem& q = probs[k];
+            memset(&q, 0, sizeof(q));
+            q.h = dH[i];
+            q.d = dD[i];
+            q.st = (DevState*)r;
+            for (int j = 0; j < 2; ++j) {
+                q.s[j] = r + p.off_s[j];
+                for (int l = 0; l < 2; ++l) q.pl[j][l] = p.split ? (void*)(r + p.off_p[j][l]) : nullptr;
+            }
+            q.s64 = (double*)(r + p.off_s64);
+            q.y = (double*)(r + p.off_y);
+            q.init_parts = (double*)(r + p.off_init_parts);
+            q.main_parts = (double*)(r + p.off_main_parts);
+            q.gersh = (double*)(r + p.off_gersh);
+            q.dstats = (double*)(r + p.off_dstats);
+            q.ldh = ldh[i];
+            q.ldd = ldd[i];
+            q.n = n[i];
+            q.np = p.np;
+            q.n_occ = n_occ[i];
+            q.want_energy = o.want_energy;
+            q.init_tiles = p.init_tiles;
+            q.main_tiles = p.main_tiles;
+            q.gersh_blocks = p.gersh_blocks;
+            q.dstats_blocks = p.dstats_blocks;
+            q.in_scale = ldexpf(1.f, p.scale_log2);
+            o_g[k + 1] = o_g[k] + p.gersh_blocks;
+            o_i[k + 1] = o_i[k] + p.init_tiles;
+            o_m[k + 1] = o_m[k] + p.main_tiles;
+            o_r[k + 1] = o_r[k] + p.ref_tiles;
+            o_d[k + 1] = o_d[k] + p.dstats_blocks;
+            // squaring layers (even: S[0] -> S[1], odd: S[1] -> S[0]) and the two refinement layers
+            for (int par = 0; par < 2; ++par) {
+                SquareArgs& a = sq[par * nt + k];
+                memset(&a, 0, sizeof(a));
+                const int in = par, out = par ^ 1;   // layer n reads S[(n-1)&1]: odd n -> par 0
+                a.x0 = p.split ? q.pl[in][0] : q.s[in];
+                a.x1 = p.split ? q.pl[in][1] : nullptr;
+                a.s_in = q.s[in];
+                a.s_out = q.s[out];
+                a.p0_out = q.pl[out][0];
+                a.p1_out = q.pl[out][1];
+                a.parts = q.main_parts;
+                a.coef = ((DevState*)r)->coef;
+                a.skip = &((DevState*)r)->skip;
+                a.np = p.np;
+                a.ld_out = p.np;
+                a.n_valid = p.np;
+                a.n_real = n[i];
+                a.T = p.main_T;
+                a.ntiles = p.main_tiles;
+                a.per = p.main_per;
+                a.out_scale = ldexpf(1.f, -2 * p.scale_log2);
+                a.in_scale = ldexpf(1.f, p.scale_log2);
+            }
+            for (int step = 0; step < 2; ++step) {
+                SquareArgs& a = sq[(2 + step) * nt + k];
+                memset(&a, 0, sizeof(a));
+                a.x0 = step == 0 ? (const void*)q.s64 : (const void*)q.y;
+                a.s_in = a.x0;
+                a.s_out = step == 0 ? (void*)q.y : (void*)q.d;
+                a.ld_out = step == 0 ? p.np : ldd[i];
+                a.n_valid = step == 0 ? p.np : n[i];
+                a.n_real = n[i];
+                a.coef = ((DevState*)r)->rcoef[step];
+                a.np = p.np;
+                a.T = p.ref_T;
+                a.ntiles = p.ref_tiles;
+                a.per = p.ref_per;
+            }
+            DevState& s0 = states[k];
+            memset(&s0, 0, sizeof(s0));
+            s0.n = n[i];
+            s0.n_occ = n_occ[i];
+            s0.n_padded = p.np;
+            s0.max_layers = o.max_layers;
+            s0.precision = o.precision;
+            s0.tile = p.tile_main;
+            s0.want_energy = o.want_energy;
+            s0.eps = o.eps;
+            s0.tol_tr = tol > 0 ? tol : 1e-6;
+            s0.tol_id = tol > 0 ? tol : 1e-6 * n[i];
+            s0.emin = 0.0;
+            s0.emax = 1.0;
+            s0.status = SP2_OK;
+        }
+        // uploads (synchronous, before anything of this call is enqueued)
+        SP2_TRY(hipStreamSynchronize(user));
+        SP2_TRY(hipMemcpy(d_probs, probs.data(), sizeof(BatchProblem) * nt, hipMemcpyHostToDevice));
+        SP2_TRY(hipMemcpy(ws + L.off_sq, sq.data(), sizeof(SquareArgs) * 4 * nt, hipMemcpyHostToDevice));
+        SP2_TRY(hipMemcpy(ws + L.off_offs, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice));
+        for (int k = 0; k < nt; ++k)
+            SP2_TRY(hipMemcpy(ws + L.region[L.nontrivial[k]], &states[k], sizeof(DevState), hipMemcpyHostToDevice));
+        const SquareArgs* d_sq = (const SquareArgs*)(ws + L.off_sq);
+        const int* d_offs = (const int*)(ws + L.off_offs);
+        const int* d_og = d_offs;
+        const int* d_oi = d_og + L.n_offs;
+        const int* d_om = d_oi + L.n_offs;
+        const int* d_or = d_om + L.n_offs;
+        const int* d_od = d_or + L.n_offs;
+
+        // ---------------------------------------------------------------- the sequence
+        hipStream_t cs = nullptr;
+        SP2_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        auto enqueue = [&](hipStream_t s) -> int {
+            SP2_TRY(launch_batch_gershgorin(d_probs, d_og, nt, o_g[nt], s));
+            SP2_TRY(launch_batch_bounds(d_probs, nt, s));
+            SP2_TRY(launch_batch_init(o.precision, d_probs, d_oi, nt, o_i[nt], s));
+            for (int layer = 1; layer <= o.max_layers + 1; ++layer) {
+                SP2_TRY(launch_batch_control(d_probs, nt, layer, s));
+                if (layer > o.max_layers) break;
+                const SquareArgs* a = d_sq + ((layer - 1) & 1) * nt;
+                if (o.precision == SP2_FP32)
+                    SP2_TRY(launch_square_plain_g(SP2_FP32, L.tile, a, d_om, nt, o_m[nt], s));
+                else
+                    SP2_TRY(launch_square_split_g(o.precision, L.tile, a, d_om, nt, o_m[nt], s));
+            }
+            SP2_TRY(launch_batch_select(d_probs, nt, 64, s));
+            SP2_TRY(launch_square_plain_g(SP2_FP64, L.plans[L.nontrivial[0]].tile_ref, d_sq + 2 * nt, d_or, nt,
+                                          o_r[nt], s));
+            SP2_TRY(launch_square_plain_g(SP2_FP64, L.plans[L.nontrivial[0]].tile_ref, d_sq + 3 * nt, d_or, nt,
+                                          o_r[nt], s));
+            SP2_TRY(launch_batch_dstats(d_probs, d_od, nt, o_d[nt], s));
+            SP2_TRY(launch_batch_finalize(d_probs, nt, s));
+            return SP2_OK;
+        };
+        int rc = SP2_OK;
+        if (use_graph) {
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = SP2_EDEVICE;
+            if (rc == SP2_OK) {
+                rc = enqueue(cs);
+                const hipError_t e = hipStreamEndCapture(cs, &graph);
+                if (rc == SP2_OK && e != hipSuccess) rc = SP2_EDEVICE;
+            }
+            if (rc == SP2_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) rc = SP2_EDEVICE;
+            if (rc == SP2_OK && hipGraphLaunch(exec, cs) != hipSuccess) rc = SP2_EDEVICE;
+            if (hipStreamSynchronize(cs) != hipSuccess && rc == SP2_OK) rc = SP2_EDEVICE;
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+        } else {
+            rc = enqueue(cs);
+            if (hipStreamSynchronize(cs) != hipSuccess && rc == SP2_OK) rc = SP2_EDEVICE;
+        }
+        (void)hipStreamDestroy(cs);
+        if (rc != SP2_OK) return rc;
+    }
+    SP2_TRY(hipStreamSynchronize(user));
+    int worst = SP2_OK;
+    for (int i = 0; i < batch; ++i) {
+        DevState host;
+        SP2_TRY(hipMemcpy(&host, ws + L.region[i], sizeof(DevState), hipMemcpyDeviceToHost));
+        if (infos) fill_info(host, &L.plans[i], &infos[i]);
+        if (host.status != SP2_OK && worst == SP2_OK) worst = host.status;
+    }
+    return worst;
 }
 
 }  // extern "C"

@@ -78,6 +78,18 @@ __device__ inline int xcd_tile_index(int b, int per, int ntiles) {
 
 inline int ntiles_upper(int T) { return T * (T + 1) / 2; }
 
+// Group of a block in a launch that covers several problems: offs[0..n] are the first
+// block of each problem (offs[0] = 0, offs[n] = total); returns p with offs[p] <= b < offs[p+1].
+__device__ inline int find_group(const int* offs, int n, int b) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (offs[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------------------------------
 // Arguments of the squaring kernels: Y = alpha X^2 + beta X + gamma I, written to
 // both triangles (exactly symmetric), optionally split into half-precision planes, with
@@ -104,11 +116,75 @@ struct SquareArgs {
     float in_scale;       // split modes: 2^s applied before splitting Y
 };
 
+// Schedule of the persistent split-square kernel: G workgroups run `rounds` whole rounds
+// of tiles, then the `tail_tiles` leftover tiles are each cut into `chunks` K-chunks.
+// `partial` holds one FP32 tile accumulator per tail chunk, `counter` one arrival count
+// per tail tile (zeroed at the start of every call; each executed layer adds `chunks`).
+constexpr int kMaxSkGrid = 1024;
+struct StreamK {
+    int grid, rounds, tail_tiles, chunks;
+    float* partial;
+    int* counter;
+};
+
+// Arguments of the FP32 adjoint layer of the generalized-SP2 network.
+struct AdjointArgs {
+    const float* g;       // G = dL/dX_{k+1}, np x np, symmetric
+    const float* x;       // X_k, np x np, symmetric
+    float* g_out;         // G_k = W_k (G X_k + X_k G) + B_k G
+    double* parts;        // 3 doubles per tile: Tr G, <G, X_k>, <G, X_k^2>
+    const float* coef;    // (W_k, B_k, c_k)
+    int np, T, ntiles, per;
+};
+
+hipError_t launch_pack_coef(const float* w, const float* b, const float* c, int K, float* out, hipStream_t s);
+hipError_t launch_copy_pad(const float* src, float* dst, int n, int ld, int np, int to_pad, hipStream_t s);
+int adjoint_grid(int tile, int np, int* T, int* ntiles, int* per);
+hipError_t launch_adjoint(int tile, const AdjointArgs& a, hipStream_t s);
+hipError_t launch_reduce3(const double* parts, int nparts, float* dw, float* db, float* dc, int k, hipStream_t s);
+
+// One problem of a batched call (device copy; pointers into the batch workspace).  The
+// batched path uses the FP32 state of the split and FP32 modes.
+struct BatchProblem {
+    const double* h;
+    double* d;
+    DevState* st;
+    void* s[2];           // FP32 states, ping-pong
+    void* pl[2][2];       // half-precision planes (split modes), ping-pong
+    double* s64;          // refinement input (FP64)
+    double* y;            // refinement intermediate (FP64)
+    double* init_parts;   // 3 per input-layer tile
+    double* main_parts;   // 2 per squaring tile
+    double* gersh;        // 3 per Gershgorin block
+    double* dstats;       // 3 per final-check block
+    int ldh, ldd, n, np, n_occ, want_energy;
+    int init_tiles, main_tiles, gersh_blocks, dstats_blocks;
+    float in_scale, pad;
+};
+
+hipError_t launch_batch_gershgorin(const BatchProblem* pr, const int* offs, int nprob, int blocks, hipStream_t s);
+hipError_t launch_batch_bounds(const BatchProblem* pr, int nprob, hipStream_t s);
+hipError_t launch_batch_init(int precision, const BatchProblem* pr, const int* offs, int nprob, int blocks,
+                             hipStream_t s);
+hipError_t launch_batch_control(const BatchProblem* pr, int nprob, int layer, hipStream_t s);
+hipError_t launch_batch_select(const BatchProblem* pr, int nprob, int per_problem, hipStream_t s);
+hipError_t launch_batch_dstats(const BatchProblem* pr, const int* offs, int nprob, int blocks, hipStream_t s);
+hipError_t launch_batch_finalize(const BatchProblem* pr, int nprob, hipStream_t s);
+
 // Host-side launchers (defined next to their kernels).
 hipError_t launch_square_split(int precision, int tile, const SquareArgs& a, hipStream_t s);
 hipError_t launch_square_plain(int precision, int tile, const SquareArgs& a, hipStream_t s);
+hipError_t launch_square_split_g(int precision, int tile, const SquareArgs* descs, const int* offs, int nprob,
+                                 int blocks, hipStream_t s);
+hipError_t launch_square_plain_g(int precision, int tile, const SquareArgs* descs, const int* offs, int nprob,
+                                 int blocks, hipStream_t s);
 int square_split_grid(int tile, int np, int* T, int* ntiles, int* per);
 int square_plain_grid(int tile, int np, int* T, int* ntiles, int* per);
+bool square_sk_plan(int tile, int np, int cus, int* wg_per_cu, StreamK* sk, int* T, int* ntiles);
+size_t square_sk_partial_bytes(int tile, int np);
+hipError_t launch_square_sk(int precision, int tile, int waves, const SquareArgs& a, const StreamK& sk,
+                            hipStream_t s);
+hipError_t launch_zero_ints(int* p, int count, hipStream_t s);
 
 // preparation / control kernels (k_prep.hip)
 hipError_t launch_state_init(DevState* st, const DevState& init, hipStream_t s);

@@ -34,6 +34,7 @@ class Options(ctypes.Structure):
         ("scale_log2", ctypes.c_int),
         ("want_energy", ctypes.c_int),
         ("tile", ctypes.c_int),
+        ("kernel", ctypes.c_int),
     ]
 
 
@@ -105,11 +106,26 @@ def lib() -> ctypes.CDLL:
     L.sp2_query.restype = c_int
     L.sp2_square_padded.argtypes = [c_int, c_int, c_int]
     L.sp2_square_padded.restype = c_int
-    L.sp2_square_workspace_size.argtypes = [c_int, c_int, c_int]
+    L.sp2_square_workspace_size.argtypes = [c_int, c_int, c_int, c_int]
     L.sp2_square_workspace_size.restype = c_size_t
-    L.sp2_square.argtypes = [c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_float, c_float, c_float,
+    L.sp2_square.argtypes = [c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_int, c_float, c_float, c_float,
                              ctypes.POINTER(c_double), c_void_p, c_size_t, c_void_p]
     L.sp2_square.restype = c_int
+    L.sp2_batched_workspace_size.argtypes = [c_int, ctypes.POINTER(c_int), ctypes.POINTER(Options)]
+    L.sp2_batched_workspace_size.restype = c_size_t
+    L.sp2_density_batched.argtypes = [c_int, ctypes.POINTER(c_void_p), ctypes.POINTER(c_int),
+                                      ctypes.POINTER(c_void_p), ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                                      ctypes.POINTER(c_int), c_double, ctypes.POINTER(Options),
+                                      ctypes.POINTER(Info), c_int, c_void_p, c_size_t, c_void_p]
+    L.sp2_density_batched.restype = c_int
+    L.sp2_net_workspace_size.argtypes = [c_int, c_int, c_int, c_int]
+    L.sp2_net_workspace_size.restype = c_size_t
+    L.sp2_net_forward.argtypes = [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_int, c_int,
+                                  c_void_p, c_int, c_void_p, c_size_t, c_void_p]
+    L.sp2_net_forward.restype = c_int
+    L.sp2_net_backward.argtypes = [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_int, c_int,
+                                   c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+    L.sp2_net_backward.restype = c_int
     _lib = L
     return L
 
@@ -121,7 +137,7 @@ def _prec(p) -> int:
 
 
 def options(precision="fp16x2", max_layers=100, eps=0.0, bounds=None, refine=True, scale_log2=-1,
-            want_energy=False, tile=0) -> Options:
+            want_energy=False, tile=0, kernel=0) -> Options:
     o = Options()
     lib().sp2_default_options(ctypes.byref(o))
     o.precision = _prec(precision)
@@ -134,6 +150,7 @@ def options(precision="fp16x2", max_layers=100, eps=0.0, bounds=None, refine=Tru
     o.scale_log2 = int(scale_log2)
     o.want_energy = 1 if want_energy else 0
     o.tile = int(tile)
+    o.kernel = int(kernel)
     return o
 
 
@@ -207,8 +224,8 @@ def timing_dict(t: Timing) -> dict:
 
 
 def density(h, n_occ: int, tol: float = 0.0, precision="fp16x2", max_layers=100, eps=0.0, bounds=None,
-            refine=True, scale_log2=-1, want_energy=False, tile=0, out=None, workspace=None, sync=True,
-            stream=None, timed=False):
+            refine=True, scale_log2=-1, want_energy=False, tile=0, kernel=0, out=None, workspace=None,
+            sync=True, stream=None, timed=False):
     """D = theta(mu I - H) with Tr D = n_occ (Alg. 1) for a symmetric FP64 CUDA tensor H.
 
     Returns (D, info) with info a dict (sync=True) or None (sync=False, nothing is
@@ -222,7 +239,7 @@ def density(h, n_occ: int, tol: float = 0.0, precision="fp16x2", max_layers=100,
     n = h.shape[0]
     if h.shape[1] != n or h.stride(1) != 1:
         raise ValueError("H must be square with unit column stride")
-    opts = options(precision, max_layers, eps, bounds, refine, scale_log2, want_energy, tile)
+    opts = options(precision, max_layers, eps, bounds, refine, scale_log2, want_energy, tile, kernel)
     need = workspace_size(n, opts)
     if need == 0:
         raise SP2Error(SP2_EINVAL, "sp2_workspace_size")
@@ -248,6 +265,49 @@ def density(h, n_occ: int, tol: float = 0.0, precision="fp16x2", max_layers=100,
     return out, (info_dict(info) if info is not None else None)
 
 
+def batched_workspace_size(sizes, opts: Optional[Options] = None) -> int:
+    arr = (ctypes.c_int * len(sizes))(*[int(v) for v in sizes])
+    return int(lib().sp2_batched_workspace_size(len(sizes), arr, ctypes.byref(opts) if opts is not None else None))
+
+
+def density_batched(hs, n_occs, tol: float = 0.0, precision="fp16x2", max_layers=100, eps=0.0, scale_log2=-1,
+                    want_energy=False, tile=0, use_graph=True, outs=None, workspace=None, stream=None):
+    """D_i = theta(mu_i I - H_i) for a list of symmetric FP64 CUDA tensors of any sizes, all
+    problems advanced together one layer per launch.  Returns (list of D_i, list of info)."""
+    import torch
+
+    b = len(hs)
+    if b == 0 or len(n_occs) != b:
+        raise ValueError("need one n_occ per Hamiltonian")
+    for h in hs:
+        if not (isinstance(h, torch.Tensor) and h.is_cuda and h.dtype == torch.float64 and h.dim() == 2
+                and h.shape[0] == h.shape[1] and h.stride(1) == 1):
+            raise TypeError("every H must be a square 2-D float64 CUDA tensor with unit column stride")
+    opts = options(precision, max_layers, eps, None, True, scale_log2, want_energy, tile, 0)
+    sizes = [int(h.shape[0]) for h in hs]
+    need = batched_workspace_size(sizes, opts)
+    if need == 0:
+        raise SP2Error(SP2_EINVAL, "sp2_batched_workspace_size")
+    dev = hs[0].device
+    if workspace is None or workspace.numel() < need:
+        workspace = alloc_workspace(need, dev)
+    if outs is None:
+        outs = [torch.empty_like(h) for h in hs]
+    infos = (Info * b)()
+    ph = (ctypes.c_void_p * b)(*[h.data_ptr() for h in hs])
+    pd = (ctypes.c_void_p * b)(*[d.data_ptr() for d in outs])
+    lh = (ctypes.c_int * b)(*[h.stride(0) for h in hs])
+    ld = (ctypes.c_int * b)(*[d.stride(0) for d in outs])
+    nn = (ctypes.c_int * b)(*sizes)
+    no = (ctypes.c_int * b)(*[int(v) for v in n_occs])
+    st = lib().sp2_density_batched(b, ph, lh, pd, ld, nn, no, float(tol), ctypes.byref(opts), infos,
+                                   1 if use_graph else 0, ctypes.c_void_p(workspace.data_ptr()),
+                                   workspace.numel(), _stream_ptr(dev, stream))
+    if st in (SP2_EDEVICE, SP2_ENOMEM) or (st == SP2_EINVAL and all(int(i.n_padded) == 0 for i in infos)):
+        raise SP2Error(st, "sp2_density_batched")
+    return outs, [info_dict(i) for i in infos]
+
+
 def query(workspace, n, precision="fp16x2", stream=None, device=None, **kw) -> dict:
     opts = options(precision, **kw)
     info = Info()
@@ -257,7 +317,7 @@ def query(workspace, n, precision="fp16x2", stream=None, device=None, **kw) -> d
 
 
 def square(x, alpha=1.0, beta=0.0, gamma=0.0, precision="fp16x2", tile=0, scale_log2=-1, workspace=None,
-           want_sums=True, stream=None):
+           want_sums=True, stream=None, kernel=0):
     """One layer Y = alpha X^2 + beta X + gamma I of a symmetric n x n CUDA tensor X (FP32 for
     the FP32/split modes, FP64 for FP64).  Returns (Y, (Tr Y, ||Y||_F^2) or None)."""
     import torch
@@ -272,13 +332,64 @@ def square(x, alpha=1.0, beta=0.0, gamma=0.0, precision="fp16x2", tile=0, scale_
     xp = torch.zeros((np_, np_), dtype=dt, device=x.device)
     xp[:n, :n] = x
     yp = torch.empty_like(xp)
-    need = L.sp2_square_workspace_size(n, p, int(tile))
+    need = L.sp2_square_workspace_size(n, p, int(tile), int(kernel))
     if workspace is None or workspace.numel() < need:
         workspace = alloc_workspace(need, x.device)
     sums = (ctypes.c_double * 2)()
     st = L.sp2_square(ctypes.c_void_p(xp.data_ptr()), ctypes.c_void_p(yp.data_ptr()), n, p, int(tile),
-                      int(scale_log2), float(alpha), float(beta), float(gamma), sums if want_sums else None,
+                      int(kernel), int(scale_log2), float(alpha), float(beta), float(gamma), sums if want_sums else None,
                       ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr(x.device, stream))
     if st != SP2_OK:
         raise SP2Error(st, "sp2_square")
     return yp[:n, :n], ((sums[0], sums[1]) if want_sums else None)
+
+
+# ------------------------------------------------------------------------------ network
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def net_workspace_size(n, K, precision="fp16x2", ckpt_every=0) -> int:
+    return int(lib().sp2_net_workspace_size(int(n), int(K), _prec(precision), int(ckpt_every)))
+
+
+def net_forward(x0, w, b, c, precision="fp16x2", ckpt_every=0, workspace=None, stream=None):
+    """X_K of the generalized-SP2 network for a symmetric FP32 CUDA tensor X_0 and FP32
+    coefficient tensors (K,).  Returns (X_K, workspace); the workspace holds the checkpoints
+    that net_backward needs."""
+    import torch
+
+    n, K = x0.shape[0], w.shape[0]
+    for t in (x0, w, b, c):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise TypeError("network tensors must be contiguous float32 CUDA tensors")
+    need = net_workspace_size(n, K, precision, ckpt_every)
+    if need == 0:
+        raise SP2Error(SP2_EINVAL, "sp2_net_workspace_size")
+    if workspace is None or workspace.numel() < need:
+        workspace = alloc_workspace(need, x0.device)
+    xk = torch.empty_like(x0)
+    st = lib().sp2_net_forward(_ptr(x0), x0.stride(0), n, K, _ptr(w), _ptr(b), _ptr(c), _prec(precision),
+                               int(ckpt_every), _ptr(xk), xk.stride(0), _ptr(workspace), workspace.numel(),
+                               _stream_ptr(x0.device, stream))
+    if st != SP2_OK:
+        raise SP2Error(st, "sp2_net_forward")
+    return xk, workspace
+
+
+def net_backward(gk, w, b, c, workspace, precision="fp16x2", ckpt_every=0, want_g0=True, stream=None):
+    """Gradients (dW, dB, dc, G_0) for G_K = dL/dX_K, after net_forward with `workspace`."""
+    import torch
+
+    n, K = gk.shape[0], w.shape[0]
+    gk = gk.contiguous()
+    dw = torch.empty_like(w)
+    db = torch.empty_like(b)
+    dc = torch.empty_like(c)
+    g0 = torch.empty_like(gk) if want_g0 else None
+    st = lib().sp2_net_backward(_ptr(gk), gk.stride(0), n, K, _ptr(w), _ptr(b), _ptr(c), _prec(precision),
+                                int(ckpt_every), _ptr(g0), gk.stride(0), _ptr(dw), _ptr(db), _ptr(dc),
+                                _ptr(workspace), workspace.numel(), _stream_ptr(gk.device, stream))
+    if st != SP2_OK:
+        raise SP2Error(st, "sp2_net_backward")
+    return dw, db, dc, g0

@@ -84,6 +84,8 @@ def test_invalid_options_give_zero_workspace():
     assert sp2.workspace_size(100, sp2.options(precision="fp64", tile=256)) == 0
     assert sp2.workspace_size(100, sp2.options(bounds=(1.0, -1.0))) == 0
     assert sp2.workspace_size(100, sp2.options(precision="fp16x2", scale_log2=15)) == 0
+    assert sp2.workspace_size(100, sp2.options(kernel=4)) == 0
+    assert sp2.workspace_size(100, sp2.options(kernel=3, tile=128)) == 0
 
 
 def test_argument_errors_return_before_device_work():
@@ -119,4 +121,37 @@ def test_square_padding_helpers():
     assert L.sp2_square_padded(300, sp2.FP16X2, 64) == 320
     assert L.sp2_square_padded(300, sp2.FP16X2, 256) == 512
     assert L.sp2_square_padded(8192, sp2.FP16X2, 0) == 8192
-    assert L.sp2_square_workspace_size(300, sp2.FP16X2, 64) > 4 * 320 * 320
+    assert L.sp2_square_workspace_size(300, sp2.FP16X2, 64, 0) > 4 * 320 * 320
+    # stream-K buffers only where that schedule can run (split modes, tiles of 128 or 256)
+    assert L.sp2_square_workspace_size(8192, sp2.FP16X2, 256, 2) > L.sp2_square_workspace_size(8192, sp2.FP16X2, 256, 1)
+    assert L.sp2_square_workspace_size(8192, sp2.FP64, 128, 2) == L.sp2_square_workspace_size(8192, sp2.FP64, 128, 1)
+
+
+def test_batched_workspace_and_argument_errors():
+    L = sp2.lib()
+    o = sp2.options()
+    sizes = [64, 130, 700]
+    total = sp2.batched_workspace_size(sizes, o)
+    singles = sum(sp2.workspace_size(n, sp2.options(tile=64, kernel=1)) for n in sizes)
+    assert total >= singles
+    assert sp2.batched_workspace_size([], o) == 0
+    assert sp2.batched_workspace_size([0, 10], o) == 0
+    assert sp2.batched_workspace_size(sizes, sp2.options(precision="fp64")) == 0
+    assert sp2.batched_workspace_size(sizes, sp2.options(bounds=(-1.0, 1.0))) == 0
+    fake = ctypes.c_void_p(256)
+    P = ctypes.c_void_p * 1
+    I = ctypes.c_int * 1
+    ph, pd = P(256), P(256)
+
+    def call(n, n_occ, ldh, ldd, work=1 << 40, ws=fake):
+        return L.sp2_density_batched(1, ph, I(ldh), pd, I(ldd), I(n), I(n_occ), 0.0, ctypes.byref(o), None, 1,
+                                     ws, work, None)
+
+    assert call(10, 5, 9, 10) == sp2.SP2_EINVAL
+    assert call(10, 5, 10, 9) == sp2.SP2_EINVAL
+    assert call(10, 11, 10, 10) == sp2.SP2_EINVAL
+    assert call(0, 0, 1, 1) == sp2.SP2_EINVAL
+    assert call(10, 5, 10, 10, ws=ctypes.c_void_p(260)) == sp2.SP2_EINVAL
+    assert call(10, 5, 10, 10, work=16) == sp2.SP2_ENOMEM
+    assert L.sp2_density_batched(0, ph, I(10), pd, I(10), I(10), I(5), 0.0, ctypes.byref(o), None, 1, fake,
+                                 1 << 40, None) == sp2.SP2_EINVAL

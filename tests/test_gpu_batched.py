@@ -1,0 +1,83 @@
+"""Batched solve (many Hamiltonians of different sizes advanced together, one launch per
+layer, optionally as one hipGraph): every problem must give exactly what the
+single-problem path gives with the same tile and one-workgroup-per-tile schedule, and
+the accuracy the oracle's eigendecomposition fixes (D = theta(mu I - H), Tr D = N_occ)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import dm
+from paper_2101_06385_amd import sp2, workloads as wl
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _check_vs_oracle(w, d, info):
+    ref = dm.dm_construct(w.q, w.eps, w.n_occ)
+    got = d.cpu().numpy()
+    fro = np.linalg.norm(got - ref)
+    assert info["status"] == 0, info["status_name"]
+    assert fro <= 1e-3 * np.sqrt(w.n), (w.name, fro)
+    assert abs(np.trace(got) - w.n_occ) <= 1e-6, (w.name, np.trace(got) - w.n_occ)
+
+
+@pytest.mark.parametrize("prec", ["fp16x2", "bf16x2", "fp32"])
+def test_batched_matches_single_path_bitwise(prec):
+    ws = [wl.gapped(40 + i, n, n // 3) for i, n in enumerate((64, 130, 200, 257, 384))]
+    hs = [torch.from_numpy(w.h).to(DEV) for w in ws]
+    outs, infos = sp2.density_batched(hs, [w.n_occ for w in ws], precision=prec, tile=64)
+    for w, h, d, info in zip(ws, hs, outs, infos):
+        d1, i1 = sp2.density(h, w.n_occ, precision=prec, tile=64, kernel=1)
+        assert info["layers"] == i1["layers"] and info["sigma"] == i1["sigma"]
+        assert torch.equal(d, d1), w.name
+        if prec != "bf16x2":
+            _check_vs_oracle(w, d, info)
+
+
+def test_batched_graph_and_stream_launch_agree():
+    ws = [wl.gapped(60 + i, n, int(0.4 * n)) for i, n in enumerate((100, 300, 520))]
+    hs = [torch.from_numpy(w.h).to(DEV) for w in ws]
+    a, ia = sp2.density_batched(hs, [w.n_occ for w in ws], use_graph=True)
+    b, ib = sp2.density_batched(hs, [w.n_occ for w in ws], use_graph=False)
+    for x, y, p, q in zip(a, b, ia, ib):
+        assert torch.equal(x, y) and p["layers"] == q["layers"]
+
+
+def test_batched_config4_subset_vs_oracle():
+    """The batched workload's generator (sizes 64*U{4..48}, mixed occupations and gaps):
+    the first 12 problems, each checked against its eigendecomposition."""
+    ws = wl.config4(count=12)
+    hs = [torch.from_numpy(w.h).to(DEV) for w in ws]
+    outs, infos = sp2.density_batched(hs, [w.n_occ for w in ws])
+    for w, d, info in zip(ws, outs, infos):
+        _check_vs_oracle(w, d, info)
+        assert np.array_equal(d.cpu().numpy(), d.cpu().numpy().T)
+
+
+def test_batched_with_trivial_and_single_problems():
+    ws = [wl.gapped(70, 150, 50), wl.gapped(71, 90, 30)]
+    hs = [torch.from_numpy(w.h).to(DEV) for w in ws]
+    outs, infos = sp2.density_batched(hs + [hs[1]], [ws[0].n_occ, 0, 90])
+    _check_vs_oracle(ws[0], outs[0], infos[0])
+    assert torch.count_nonzero(outs[1]) == 0
+    assert torch.equal(outs[2], torch.eye(90, dtype=torch.float64, device=DEV))
+    one, io = sp2.density_batched(hs[:1], [ws[0].n_occ])
+    assert torch.equal(one[0], outs[0])
+
+
+def test_batched_strided_inputs_and_outputs():
+    w = wl.gapped(80, 200, 70)
+    big = torch.zeros((200, 256), dtype=torch.float64, device=DEV)
+    big[:, :200] = torch.from_numpy(w.h)
+    h = big[:, :200]
+    dbig = torch.full((200, 240), 7.0, dtype=torch.float64, device=DEV)
+    outs, infos = sp2.density_batched([h], [w.n_occ], outs=[dbig[:, :200]])
+    _check_vs_oracle(w, outs[0], infos[0])
+    assert torch.all(dbig[:, 200:] == 7.0)
+
+
+def test_batched_rejects_fp64_and_bounds():
+    h = torch.eye(64, dtype=torch.float64, device=DEV)
+    with pytest.raises(sp2.SP2Error):
+        sp2.density_batched([h], [10], precision="fp64")

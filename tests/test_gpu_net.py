@@ -1,0 +1,152 @@
+"""Parity of the differentiable generalized-SP2 network (Eq. general SP2 on matrices)
+against the CPU oracle: forward layers, the hand-written adjoint (dW, dB, dc and dL/dX_0),
+checkpoint recomputation, and the autograd wrapper."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import dm, net as onet, sp2 as osp2
+from paper_2101_06385_amd import net as gnet, sp2, workloads as wl
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _problem(n, k, seed, spread=0.02):
+    w = wl.config5(seed=seed, n=n)
+    e1, en = osp2.gershgorin(w.h)
+    x0 = osp2.rescale(w.h, e1, en).astype(np.float32)       # the input layer S_0, as FP32
+    lam0 = (en - w.eps) / (en - e1)
+    sig = osp2.sp2_eigen(lam0, n // 2, max_layers=k).sigma
+    sig = (sig + [1, -1] * k)[:k]
+    wt, bt, ct = onet.sp2_branch_coefficients(sig)
+    rng = np.random.default_rng(seed)
+    wt = (wt + rng.normal(0, spread, k)).astype(np.float32)
+    bt = (bt + rng.normal(0, spread, k)).astype(np.float32)
+    ct = (ct + rng.normal(0, spread / 4, k)).astype(np.float32)
+    target = dm.dm_fermi(w.q, w.eps, 0.0, 0.2)
+    return w, x0, wt, bt, ct, target
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@pytest.mark.parametrize("prec,n,k", [("fp32", 200, 6), ("fp16x2", 200, 6), ("bf16x2", 130, 4), ("fp16x2", 520, 10)])
+def test_forward_matches_fp64_layers(prec, n, k):
+    w, x0, wt, bt, ct, _ = _problem(n, k, 10 + n)
+    xk, _ = sp2.net_forward(_t(x0), _t(wt), _t(bt), _t(ct), precision=prec)
+    ref = onet.forward_matrix(x0.astype(np.float64), wt.astype(np.float64), bt.astype(np.float64),
+                              ct.astype(np.float64))[-1]
+    got = xk.cpu().numpy().astype(np.float64)
+    tol = {"fp32": 2e-5, "fp16x2": 2e-4, "bf16x2": 2e-3}[prec]
+    assert np.abs(got - ref).max() <= tol * max(1.0, np.abs(ref).max()), float(np.abs(got - ref).max())
+    assert np.array_equal(got, got.T)
+
+
+def test_sp2_branch_coefficients_reproduce_alg1_chain():
+    w = wl.gapped(12, 300, 100)
+    res = osp2.sp2_alg1(w.h, w.n_occ)
+    x0 = osp2.rescale(w.h, *res.bounds).astype(np.float32)
+    sig = res.sigma[:12]
+    wt, bt, ct = [a.astype(np.float32) for a in onet.sp2_branch_coefficients(sig)]
+    xk, _ = sp2.net_forward(_t(x0), _t(wt), _t(bt), _t(ct), precision="fp32")
+    ref = onet.forward_matrix(x0.astype(np.float64), *onet.sp2_branch_coefficients(sig))[-1]
+    assert np.abs(xk.cpu().numpy() - ref).max() < 1e-4
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16x2"])
+def test_adjoint_matches_oracle_gradient(prec):
+    n, k = 256, 8
+    w, x0, wt, bt, ct, target = _problem(n, k, 3)
+    xt, wtt, btt, ctt = _t(x0), _t(wt), _t(bt), _t(ct)
+    xk, ws = sp2.net_forward(xt, wtt, btt, ctt, precision=prec)
+    gk = 2.0 * (xk.double() - _t(target)).float()
+    dw, db, dc, g0 = sp2.net_backward(gk, wtt, btt, ctt, ws, precision=prec)
+    loss, rw, rb, rc, rg = onet.loss_grad_matrix(x0.astype(np.float64), target, wt.astype(np.float64),
+                                                 bt.astype(np.float64), ct.astype(np.float64))
+    tol = 2e-4 if prec == "fp32" else 2e-3
+    for got, ref in ((dw, rw), (db, rb), (dc, rc)):
+        got = got.cpu().numpy().astype(np.float64)
+        assert np.abs(got - ref).max() <= tol * np.abs(ref).max(), (prec, got, ref)
+    g0n = g0.cpu().numpy().astype(np.float64)
+    assert np.abs(g0n - rg).max() <= tol * np.abs(rg).max()
+
+
+def test_adjoint_matches_central_differences_of_the_gpu_forward():
+    """FP32 layers, h = 1e-2: the GPU backward equals the slope of the GPU forward."""
+    n, k = 128, 5
+    w, x0, wt, bt, ct, target = _problem(n, k, 4)
+    xt, tt = _t(x0), _t(target)
+
+    def loss(wv, bv, cv):
+        xk, _ = sp2.net_forward(xt, _t(wv), _t(bv), _t(cv), precision="fp32")
+        return float(((xk.double() - tt) ** 2).sum())
+
+    xk, ws = sp2.net_forward(xt, _t(wt), _t(bt), _t(ct), precision="fp32")
+    dw, db, dc, _ = sp2.net_backward((2.0 * (xk.double() - tt)).float(), _t(wt), _t(bt), _t(ct), ws,
+                                     precision="fp32", want_g0=False)
+    h = 1e-2
+    for arr_i, grad in ((0, dw), (1, db), (2, dc)):
+        for j in (0, k // 2, k - 1):
+            p = [wt.copy(), bt.copy(), ct.copy()]
+            m = [wt.copy(), bt.copy(), ct.copy()]
+            p[arr_i][j] += h
+            m[arr_i][j] -= h
+            fd = (loss(*p) - loss(*m)) / (2 * h)
+            assert abs(fd - float(grad[j])) <= 2e-2 * max(1.0, abs(fd)), (arr_i, j, fd, float(grad[j]))
+
+
+def test_checkpoint_recompute_is_bit_identical():
+    n, k = 200, 9
+    w, x0, wt, bt, ct, target = _problem(n, k, 5)
+    outs = []
+    for c in (1, 3, 9, 0):
+        xk, ws = sp2.net_forward(_t(x0), _t(wt), _t(bt), _t(ct), precision="fp16x2", ckpt_every=c)
+        gk = (2.0 * (xk.double() - _t(target))).float()
+        outs.append([xk] + list(sp2.net_backward(gk, _t(wt), _t(bt), _t(ct), ws, precision="fp16x2",
+                                                 ckpt_every=c)))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert torch.equal(a, b)
+
+
+def test_autograd_module_trains():
+    n, k = 256, 10
+    w, x0, wt, bt, ct, target = _problem(n, k, 6, spread=0.0)
+    lam0 = (osp2.gershgorin(w.h)[1] - w.eps) / (osp2.gershgorin(w.h)[1] - osp2.gershgorin(w.h)[0])
+    sig = osp2.sp2_eigen(lam0, n // 2, max_layers=k).sigma
+    model = gnet.SP2Net((sig + [1, -1] * k)[:k], precision="fp16x2", device=DEV)
+    xt, tt = _t(x0), _t(target).float()
+    opt = torch.optim.Adam(model.parameters(), lr=3e-3)
+    losses = []
+    for _ in range(15):
+        opt.zero_grad()
+        loss = ((model(xt) - tt) ** 2).sum()
+        loss.backward()
+        opt.step()
+        losses.append(float(loss))
+    assert np.isfinite(losses).all()
+    assert losses[-1] < 0.7 * losses[0], losses
+
+
+def test_config5_full_size_loss_and_gradient():
+    """N = 2048, 20 layers, kT = 0.2 eV target: the matrix loss and gradient against the
+    exact eigenvalue-space loss and gradient of the same coefficients (FP64 oracle)."""
+    n, k = 2048, 20
+    w, x0, wt, bt, ct, target = _problem(n, k, 5000, spread=0.0)
+    e1, en = osp2.gershgorin(w.h)
+    lam0 = (en - w.eps) / (en - e1)
+    tvals = dm.fermi_dirac(w.eps, 0.0, 0.2)
+    xt = _t(x0)
+    xk, ws = sp2.net_forward(xt, _t(wt), _t(bt), _t(ct), precision="fp16x2")
+    diff = xk.double() - _t(target)
+    loss = float((diff ** 2).sum())
+    dw, db, dc, _ = sp2.net_backward((2.0 * diff).float(), _t(wt), _t(bt), _t(ct), ws, precision="fp16x2",
+                                     want_g0=False)
+    rl, rw, rb, rc, _ = onet.loss_grad_scalar(lam0, tvals, wt.astype(np.float64), bt.astype(np.float64),
+                                              ct.astype(np.float64))
+    assert abs(loss - rl) <= 1e-3 * rl + 1e-2, (loss, rl)
+    for got, ref in ((dw, rw), (db, rb), (dc, rc)):
+        g = got.cpu().numpy().astype(np.float64)
+        assert np.abs(g - ref).max() <= 2e-2 * np.abs(ref).max() + 1e-3, (g[:4], ref[:4])

@@ -78,6 +78,47 @@ def test_plain_square_vs_fp64(prec, tile, n):
         _check_sums(y, sums)
 
 
+@pytest.mark.parametrize("prec,tile,kernel,n", [
+    ("fp16x2", 256, 2, 6100), ("fp16x2", 256, 3, 6100), ("fp16x2", 128, 2, 4100), ("bf16x2", 256, 2, 6100),
+    ("fp16x2", 256, 1, 6100),
+])
+def test_persistent_schedules_sampled_rows(prec, tile, kernel, n):
+    """Stream-K schedules (only used once there are at least as many tiles as
+    workgroups, hence the large n): sampled rows against the oracle's exact products."""
+    fmt = "fp16" if prec == "fp16x2" else "bf16"
+    s = 12 if fmt == "fp16" else 0
+    rng = np.random.default_rng(n + kernel)
+    a = rng.standard_normal((n, n)).astype(np.float32) / np.float32(np.sqrt(n))
+    x = (a + a.T) * np.float32(0.5)
+    rows = [0, 1, 255, 256, 1000, n // 2, n - 1]
+    x0, x1 = osp2.split_planes(x, fmt, s)
+    a0, a1 = np.abs(x0.astype(np.float64)), np.abs(x1.astype(np.float64))
+    mag = (a0[rows] @ a0 + a0[rows] @ a1 + a1[rows] @ a0) * 2.0 ** (-2 * s)
+    ref = osp2.mixed_square_rows(x, rows, fmt, s)
+    for alpha, beta, gamma in COEFS[:2]:
+        y, sums = sp2.square(torch.from_numpy(x).to(DEV), alpha, beta, gamma, precision=prec, tile=tile,
+                             kernel=kernel)
+        assert torch.equal(y, y.T)
+        yr = y[rows].cpu().numpy().astype(np.float64)
+        want = alpha * ref + beta * x[rows].astype(np.float64) + gamma * np.eye(n)[rows]
+        bound = 2.0 * n * U32 * mag + 2.0 * U32 * (np.abs(alpha * ref) + abs(beta) * np.abs(x[rows]))
+        err = np.abs(yr - want)
+        assert np.all(err <= bound + 1e-30), float((err / (bound + 1e-30)).max())
+        tr = float(torch.trace(y.double()))
+        fr = float((y.double() ** 2).sum())
+        assert abs(sums[0] - tr) <= 1e-10 * max(1.0, abs(tr)) and abs(sums[1] - fr) <= 1e-10 * fr
+
+
+def test_persistent_schedule_deterministic():
+    n = 6100
+    rng = np.random.default_rng(1)
+    a = rng.standard_normal((n, n)).astype(np.float32) / np.float32(np.sqrt(n))
+    x = torch.from_numpy((a + a.T) * np.float32(0.5)).to(DEV)
+    y1, s1 = sp2.square(x, precision="fp16x2", tile=256, kernel=2)
+    y2, s2 = sp2.square(x, precision="fp16x2", tile=256, kernel=2)
+    assert torch.equal(y1, y2) and s1 == s2
+
+
 def test_split_square_paper_mode_without_shift():
     """scale_log2 = 0 is the paper's split exactly (Eqs. Split1/Split2)."""
     n = 256

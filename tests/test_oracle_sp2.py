@@ -237,6 +237,14 @@ def test_mixed_square_brute_force_rational():
     assert np.array_equal(got, got.T)
 
 
+def test_mixed_square_rows_match_full_product():
+    w = wl.gapped(13, 90, 30)
+    x = sp2.rescale(w.h, *sp2.gershgorin(w.h)).astype(np.float32)
+    rows = [0, 17, 89]
+    for fmt, s in (("fp16", 12), ("bf16", 0)):
+        assert np.abs(sp2.mixed_square_rows(x, rows, fmt, s) - sp2.mixed_square(x, fmt, s)[rows]).max() < 1e-15
+
+
 def test_mixed_square_exact_for_half_representable_input():
     rng = np.random.default_rng(4)
     a = rng.integers(-8, 9, size=(16, 16)).astype(np.float32) / 16
