@@ -72,8 +72,12 @@ typedef struct {
     int want_energy;   /* nonzero: info->energy = Tr[D H] (the observable of Alg. 1) */
     int tile;          /* output tile edge of the squaring kernels: 0 = automatic, or 64/128/256 */
     int kernel;        /* split-mode squaring schedule: 0 = automatic, 1 = one workgroup per
-                          tile, 2 = persistent stream-K with 4 wavefronts per workgroup,
-                          3 = persistent stream-K with 8 wavefronts (256 tiles only) */
+                          tile, 2..5 = persistent schedule (whole rounds of tiles, then the
+                          leftover tiles split along K), kernel variant 0..3 for the tile:
+                            256: (4 waves, 16-half K-slices, 4 LDS stages), (8, 16, 4),
+                                 (4, 32, 2), (8, 32, 2)
+                            128: (4, 32, 4), (4, 64, 2), (4, 16, 4), (4, 32, 2)
+                          Only split modes with tiles of 128/256 use it; otherwise ignored. */
 } sp2_options;
 
 typedef struct {

@@ -20,7 +20,7 @@ namespace sp2 {
 namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_adjoint(AdjointArgs a) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[m][n][r] = 0.f;
 
-    u32x4 stg[4][CPT];
+    f32x4 stg[4][CPT];
     auto gload = [&](int k0) {
 #pragma unroll
         for (int arr = 0; arr < 4; ++arr)
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_adjoint(AdjointArgs a) {
             for (int i = 0; i < CPT; ++i) {
                 const int q = tid + i * NT;
                 const int r = q / CPR, c = q % CPR;
-                stg[arr][i] = *(const u32x4*)(src[arr] + (size_t)r * np + k0 + c * 4);
+                stg[arr][i] = *(const f32x4*)(src[arr] + (size_t)r * np + k0 + c * 4);
             }
     };
     auto lstore = [&](int buf) {
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_adjoint(AdjointArgs a) {
                 const int r = q / CPR, c = q % CPR;
                 float* dst = lds + (buf * 4 + arr) * ARR + r * LROW + c * 4;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) dst[e] = __builtin_bit_cast(float, stg[arr][i][e]);
+                for (int e = 0; e < 4; ++e) dst[e] = stg[arr][i][e];
             }
     };
 

@@ -1,418 +1,53 @@
-// Split (dual half-precision) squaring layer, persistent version (gfx950).
-//
-// Computes the same layer as k_square_split (Y = alpha X^2 + beta X + gamma I from the
-// planes X0, X1 with the product X0 X0 + X0 X1 + X1 X0 of Eq. Square, over the
-// upper-triangle tiles, mirrored) with G persistent workgroups:
-//
-//  * Whole rounds: tiles [0, R G) go round by round, workgroup v taking tile r G + v in
-//    round r.  Every round starts at K = 0 on every CU, and the workgroups of one XCD
-//    hold consecutive tiles of the strip order, so they stream the same panel slices at
-//    the same time and share them in that XCD's L2.
-//  * Split tail: the rem = ntiles - R G tiles left over are each cut into s = G / rem
-//    K-chunks, one per workgroup, so the last round takes 1/s of a round instead of a
-//    full one (528 tiles of 256^2 on 256 CUs: 2 rounds + 1/16 instead of 3).  Each chunk
-//    stores its FP32 partial; the last of the s arrivals sums the s partials in chunk
-//    order and runs the epilogue, so results are bit-reproducible.
-//  * Staging: slices of the row panels go straight from global memory into LDS
-//    (global_load_lds_dwordx4; each lane moves 16 bytes, a wavefront fills 1 KB of 16
-//    swizzled rows), double buffered, so no VGPRs hold staged data.
-//  * Fragments are double buffered in registers: while the matrix cores work on one
-//    K/2 half-slice, the LDS reads of the next half are in flight.
+// Host side of the persistent split squaring schedule: variant table, schedule plan
+// and dispatch to the kernel instantiations (k_sk_f16.hip, k_sk_bf16.hip).
 #include "sp2_internal.h"
 
-#include <type_traits>
-
 namespace sp2 {
-namespace {
-
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <typename T16>
-struct H2;
-template <>
-struct H2<_Float16> {
-    typedef f16x8 vec8;
-    typedef f16x4 vec4;
-    __device__ static inline f32x16 mfma(vec8 a, vec8 b, f32x16 c) {
-        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
-    }
+hipError_t launch_sk_t(int tile, int variant, const SquareArgs& a, const StreamK& sk, hipStream_t s);
+extern template hipError_t launch_sk_t<_Float16>(int, int, const SquareArgs&, const StreamK&, hipStream_t);
+extern template hipError_t launch_sk_t<__bf16>(int, int, const SquareArgs&, const StreamK&, hipStream_t);
+
+// Variants of the persistent kernel per tile edge: (waves, slice width in halves, LDS stages).
+// Selected by index; the measured best is the automatic choice of the host driver.
+namespace {
+struct SkVariant {
+    int waves, sk, stages;
 };
-template <>
-struct H2<__bf16> {
-    typedef bf16x8 vec8;
-    typedef bf16x4 vec4;
-    __device__ static inline f32x16 mfma(vec8 a, vec8 b, f32x16 c) {
-        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-    }
-};
-
-constexpr int kSK = 16;          // halves per panel row per K-slice (one MFMA K step)
-constexpr int kRow = kSK * 2;    // bytes per LDS row of a slice
-constexpr int kStages = 4;       // slices resident in LDS; loads run kStages - 1 slices ahead
-
-// Swizzle of the two 16-byte chunks of a 32-byte LDS row: row r stores logical chunk c
-// at physical position c ^ swz(r).  gfx950 serves a ds_read_b128 16 lanes at a time
-// from 64 banks; the 16 rows a lane group reads at one logical chunk then fall on 16
-// distinct groups of four banks.
-__device__ inline int swz(int r) { return (r >> 3) & 1; }
-
-// Compile-time loop: f(integral_constant<int, i>) for i in [B, E).  Keeps every index
-// into the accumulator array a constant, so the accumulators stay in registers.
-template <int B, int E, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-    if constexpr (B < E) {
-        f(std::integral_constant<int, B>{});
-        static_for<B + 1, E>(f);
-    }
+constexpr SkVariant kV256[kSkVariants] = {{4, 16, 4}, {8, 16, 4}, {4, 32, 2}, {8, 32, 2}};
+constexpr SkVariant kV128[kSkVariants] = {{4, 32, 4}, {4, 64, 2}, {4, 16, 4}, {4, 32, 2}};
+const SkVariant* sk_variant(int tile, int variant) {
+    if (variant < 0 || variant >= kSkVariants) return nullptr;
+    if (tile == 256) return &kV256[variant];
+    if (tile == 128) return &kV128[variant];
+    return nullptr;
 }
-
-__device__ inline double wsum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// s_waitcnt needs an immediate: wait until at most n vector-memory instructions of this
-// wavefront are outstanding, for the counts the pipeline below can ask for.
-#define SP2_VMCNT(n) asm volatile("s_waitcnt vmcnt(" #n ")" ::: "memory")
-__device__ __forceinline__ void wait_vm(int n) {
-    switch (n) {
-        case 24: SP2_VMCNT(24); break;
-        case 16: SP2_VMCNT(16); break;
-        case 12: SP2_VMCNT(12); break;
-        case 8: SP2_VMCNT(8); break;
-        case 4: SP2_VMCNT(4); break;
-        default: SP2_VMCNT(0); break;
-    }
-}
-#undef SP2_VMCNT
-
-template <typename T16, int WM, int WN, int MB, int NB>
-struct Cfg {
-    static constexpr int NW = WM * WN;
-    static constexpr int NT = 64 * NW;
-    static constexpr int WTM = MB * 32, WTN = NB * 32;
-    static constexpr int BT = WM * WTM;
-    static_assert(BT == WN * WTN, "square tiles only");
-    static constexpr int ARR = BT * kRow;          // bytes of one panel slice in LDS
-    static constexpr int STAGE = 4 * ARR;          // A0, A1, B0, B1
-    static constexpr int BPR = BT / 32;            // 1 KB blocks (32 rows) per panel slice
-    static constexpr int LPW = 4 * BPR / NW;       // direct-load instructions per wave per slice
-    static_assert((4 * BPR) % NW == 0, "slice blocks must split evenly over waves");
-};
-
-template <typename T16, int WM, int WN, int MB, int NB>
-__global__ __launch_bounds__(64 * WM * WN) void k_square_sk(SquareArgs a, StreamK sk) {
-    typedef Cfg<T16, WM, WN, MB, NB> C;
-    typedef typename H2<T16>::vec8 vec8;
-    typedef typename H2<T16>::vec4 vec4;
-    constexpr int BT = C::BT;
-    constexpr int LPW = C::LPW;
-
-    __shared__ __attribute__((aligned(16))) unsigned char lds[kStages * C::STAGE];
-    __shared__ int s_flag;
-
-    if (a.skip && *a.skip) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave / WN, wn = wave % WN;
-    const int np = a.np;
-    const int KS = np / kSK;    // K-slices per tile
-    // XCD-aware order: the workgroups of one XCD get consecutive virtual indices
-    const int G = sk.grid;
-    const int v = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
-
-    // lane L of a direct load fills LDS bytes [16 L, 16 L + 16) of a 32-row block: row
-    // L / 2, physical chunk L % 2, i.e. logical chunk (L % 2) ^ swz(L / 2)
-    const int loff = (lane >> 1) * np + (((lane & 1) ^ ((lane >> 4) & 1)) << 3);
-    // fragment read offsets (bytes) inside a slice buffer: row r = base + lane % 32,
-    // logical chunk lane / 32
-    const int rsub = lane & 31;
-    const int fchunk = ((lane >> 5) ^ swz(rsub)) << 4;
-
-    const T16* x0 = (const T16*)a.x0;
-    const T16* x1 = (const T16*)a.x1;
-    const float alpha = a.coef[0], beta = a.coef[1], gamma = a.coef[2];
-
-    // work items: whole rounds, then at most one tail chunk
-    const int items = sk.rounds + ((sk.tail_tiles > 0 && v < sk.tail_tiles * sk.chunks) ? 1 : 0);
-    for (int item = 0; item < items; ++item) {
-        int t, kb, ke, chunk = -1, tail_tile = 0;
-        if (item < sk.rounds) {
-            t = item * G + v;
-            kb = 0;
-            ke = KS;
-        } else {
-            tail_tile = v / sk.chunks;
-            chunk = v % sk.chunks;
-            t = sk.rounds * G + tail_tile;
-            kb = (int)(((long long)chunk * KS) / sk.chunks);
-            ke = (int)(((long long)(chunk + 1) * KS) / sk.chunks);
-        }
-        int I, J;
-        tile_of(t, a.T, 8, &I, &J);
-        const T16* src[4] = {x0 + (size_t)I * BT * np, x1 + (size_t)I * BT * np, x0 + (size_t)J * BT * np,
-                             x1 + (size_t)J * BT * np};
-
-        auto issue = [&](int buf, int ks) {
-#pragma unroll
-            for (int i = 0; i < LPW; ++i) {
-                const int j = wave * LPW + i;
-                const int arr = j / C::BPR;
-                const int qd = j % C::BPR;
-                const T16* g = src[arr] + (size_t)(qd * 32) * np + ks * kSK + loff;
-                __builtin_amdgcn_global_load_lds((const void*)g,
-                                                 (void*)(lds + buf * C::STAGE + arr * C::ARR + qd * 32 * kRow),
-                                                 16, 0, 0);
-            }
-        };
-        auto frags = [&](int buf, vec8 (&fa0)[MB], vec8 (&fa1)[MB], vec8 (&fb0)[NB], vec8 (&fb1)[NB]) {
-            const unsigned char* base = lds + buf * C::STAGE + rsub * kRow + fchunk;
-#pragma unroll
-            for (int m = 0; m < MB; ++m) {
-                const int off = (wm * C::WTM + m * 32) * kRow;
-                fa0[m] = *(const vec8*)(base + off);
-                fa1[m] = *(const vec8*)(base + C::ARR + off);
-            }
-#pragma unroll
-            for (int n = 0; n < NB; ++n) {
-                const int off = (wn * C::WTN + n * 32) * kRow;
-                fb0[n] = *(const vec8*)(base + 2 * C::ARR + off);
-                fb1[n] = *(const vec8*)(base + 3 * C::ARR + off);
-            }
-        };
-
-        f32x16 acc[MB][NB];
-#pragma unroll
-        for (int m = 0; m < MB; ++m)
-#pragma unroll
-            for (int n = 0; n < NB; ++n)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) acc[m][n][r] = 0.f;
-
-        auto mma = [&](const vec8 (&fa0)[MB], const vec8 (&fa1)[MB], const vec8 (&fb0)[NB], const vec8 (&fb1)[NB]) {
-#pragma unroll
-            for (int m = 0; m < MB; ++m)
-#pragma unroll
-                for (int n = 0; n < NB; ++n) acc[m][n] = H2<T16>::mfma(fa0[m], fb0[n], acc[m][n]);
-#pragma unroll
-            for (int m = 0; m < MB; ++m)
-#pragma unroll
-                for (int n = 0; n < NB; ++n) acc[m][n] = H2<T16>::mfma(fa0[m], fb1[n], acc[m][n]);
-#pragma unroll
-            for (int m = 0; m < MB; ++m)
-#pragma unroll
-                for (int n = 0; n < NB; ++n) acc[m][n] = H2<T16>::mfma(fa1[m], fb0[n], acc[m][n]);
-        };
-
-        // ---------------------------------------------------------------- main loop
-        // slice kb + j lives in LDS buffer j % kStages.  Prologue: the first kStages
-        // slices in flight, the first one landed and read into fragment set P.
-        wait_vm(0);   // nothing of the previous item may still count against vmcnt
-        const int nsl = ke - kb;
-        const int pro = nsl < kStages ? nsl : kStages;     // slices 0 .. kStages - 1 in flight
-        for (int q = 0; q < pro; ++q) issue(q, kb + q);
-        wait_vm((pro - 1) * LPW);   // the first slice has landed
-        __syncthreads();
-        vec8 pa0[MB], pa1[MB], pb0[NB], pb1[NB];   // fragments of even slices
-        vec8 qa0[MB], qa1[MB], qb0[NB], qb1[NB];   // fragments of odd slices
-        frags(0, pa0, pa1, pb0, pb1);
-        // Make slice `next` readable (its loads landed, every wave past the barrier, so
-        // the buffer of slice next - 1, already read into registers, is free) and refill
-        // that buffer with slice next + kStages - 1.  Invariant on entry: slices up to
-        // next + kStages - 2 have been issued.  The caller then reads `next`'s fragments.
-        auto advance = [&](int next) {
-            const int issued = (next + kStages - 1 < nsl) ? next + kStages - 1 : nsl;   // slices issued so far
-            const int later = issued - (next + 1);
-            wait_vm((later > 0 ? later : 0) * LPW);
-            __syncthreads();
-            if (next + kStages - 1 < nsl) issue((next - 1) % kStages, kb + next + kStages - 1);
-        };
-        int j = 0;
-        for (; j + 2 <= nsl; j += 2) {
-            advance(j + 1);
-            frags((j + 1) % kStages, qa0, qa1, qb0, qb1);
-            mma(pa0, pa1, pb0, pb1);
-            if (j + 2 < nsl) {
-                advance(j + 2);
-                frags((j + 2) % kStages, pa0, pa1, pb0, pb1);
-            }
-            mma(qa0, qa1, qb0, qb1);
-        }
-        if (j < nsl) mma(pa0, pa1, pb0, pb1);   // odd slice count: the last slice
-        __syncthreads();   // all fragment reads done before LDS is reused below
-
-        // Per-lane index arithmetic below is recomputed from an opaque copy of the thread
-        // index: otherwise it is loop-invariant across work items, gets hoisted above the
-        // main loop and takes registers the pipeline needs.
-        int otid = tid;
-        asm volatile("" : "+v"(otid));
-        const int olane = otid & 63, owave = otid >> 6;
-        const int owm = owave / WN, own = owave % WN;
-
-        // ---------------------------------------------------------------- split tail
-        bool finish = chunk < 0;
-        if (!finish) {
-            constexpr size_t TILE_F = (size_t)BT * BT;
-            // layout: per wave, per (m, n, quarter), 64 lanes x 4 floats; walked with one
-            // running pointer so that no per-block addresses are kept live
-            f32x4* wp = (f32x4*)(sk.partial + (size_t)v * TILE_F + (size_t)owave * MB * NB * 16 * 64) + olane;
-            static_for<0, MB>([&](auto m) {
-                static_for<0, NB>([&](auto n) {
-                    static_for<0, 4>([&](auto q4) {
-                        f32x4 vv = {acc[m][n][4 * q4], acc[m][n][4 * q4 + 1], acc[m][n][4 * q4 + 2],
-                                    acc[m][n][4 * q4 + 3]};
-                        *wp = vv;
-                        wp += 64;
-                    });
-                });
-            });
-            __threadfence();
-            __syncthreads();
-            if (tid == 0) s_flag = atomicAdd(sk.counter + tail_tile, 1);
-            __syncthreads();
-            // each executed layer adds `chunks` arrivals per tail tile: the last one reduces
-            finish = ((s_flag + 1) % sk.chunks) == 0;
-            if (finish) {
-                __threadfence();
-                const f32x4* rp = (const f32x4*)(sk.partial + (size_t)tail_tile * sk.chunks * TILE_F +
-                                                 (size_t)owave * MB * NB * 16 * 64) + olane;
-                const size_t cstride = TILE_F / 4;   // f32x4 elements between chunks
-                static_for<0, MB>([&](auto m) {
-                    static_for<0, NB>([&](auto n) {
-                        static_for<0, 4>([&](auto q4) {
-                            f32x4 sum = rp[0];
-                            for (int c = 1; c < sk.chunks; ++c) sum += rp[c * cstride];
-                            static_for<0, 4>([&](auto e) { acc[m][n][4 * q4 + e] = sum[(int)e]; });
-                            rp += 64;
-                        });
-                    });
-                });
-            }
-        }
-
-        // ---------------------------------------------------------------- epilogue
-        if (finish) {
-            float* so = (float*)a.s_out;
-            const float* si = (const float*)a.s_in;
-            T16* p0 = (T16*)a.p0_out;
-            T16* p1 = (T16*)a.p1_out;
-            const float osc = a.out_scale, isc = a.in_scale;
-            const bool diag = (I == J);
-            double tr = 0.0, fr = 0.0;
-            static_for<0, MB>([&](auto m) {
-                static_for<0, NB>([&](auto n) {
-                    const int col = J * BT + own * C::WTN + n * 32 + (olane & 31);
-                    static_for<0, 4>([&](auto g) {
-                        const int row0 = I * BT + owm * C::WTM + m * 32 + 8 * g + 4 * (olane >> 5);
-                        float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
-                        if (beta != 0.f) s4 = *(const float4*)(si + (size_t)col * np + row0);
-                        const float sv[4] = {s4.x, s4.y, s4.z, s4.w};
-                        float y4[4];
-                        T16 h0[4], h1[4];
-                        static_for<0, 4>([&](auto e) {
-                            const float x = acc[m][n][4 * g + e] * osc;
-                            float y = (beta != 0.f) ? fmaf(alpha, x, beta * sv[e]) : alpha * x;
-                            if (row0 + e == col && col < a.n_real) y += gamma;
-                            y4[e] = y;
-                            const float ys = y * isc;
-                            h0[e] = (T16)ys;
-                            h1[e] = (T16)(ys - (float)h0[e]);
-                        });
-                        if (!diag) {
-#pragma unroll
-                            for (int e = 0; e < 4; ++e) {
-                                const size_t off = (size_t)(row0 + e) * np + col;
-                                so[off] = y4[e];
-                                if (p0) {
-                                    p0[off] = h0[e];
-                                    p1[off] = h1[e];
-                                }
-                                fr += 2.0 * (double)y4[e] * (double)y4[e];
-                            }
-                            const size_t moff = (size_t)col * np + row0;
-                            *(float4*)(so + moff) = make_float4(y4[0], y4[1], y4[2], y4[3]);
-                            if (p0) {
-                                vec4 q0 = {h0[0], h0[1], h0[2], h0[3]};
-                                vec4 q1 = {h1[0], h1[1], h1[2], h1[3]};
-                                *(vec4*)(p0 + moff) = q0;
-                                *(vec4*)(p1 + moff) = q1;
-                            }
-                        } else {
-#pragma unroll
-                            for (int e = 0; e < 4; ++e) {
-                                const int row = row0 + e;
-                                if (row > col) continue;
-                                const size_t off = (size_t)row * np + col;
-                                so[off] = y4[e];
-                                if (p0) {
-                                    p0[off] = h0[e];
-                                    p1[off] = h1[e];
-                                }
-                                if (row < col) {
-                                    const size_t moff = (size_t)col * np + row;
-                                    so[moff] = y4[e];
-                                    if (p0) {
-                                        p0[moff] = h0[e];
-                                        p1[moff] = h1[e];
-                                    }
-                                    fr += 2.0 * (double)y4[e] * (double)y4[e];
-                                } else {
-                                    tr += (double)y4[e];
-                                    fr += (double)y4[e] * (double)y4[e];
-                                }
-                            }
-                        }
-                    });
-                });
-            });
-            if (a.parts) {
-                tr = wsum(tr);
-                fr = wsum(fr);
-                double* scr = (double*)lds;   // the stages are free: every wave passed the last barrier
-                __syncthreads();
-                if (olane == 0) {
-                    scr[2 * owave] = tr;
-                    scr[2 * owave + 1] = fr;
-                }
-                __syncthreads();
-                if (tid == 0) {
-                    double s0 = 0.0, s1 = 0.0;
-                    for (int w = 0; w < C::NW; ++w) {
-                        s0 += scr[2 * w];
-                        s1 += scr[2 * w + 1];
-                    }
-                    a.parts[2 * t] = s0;
-                    a.parts[2 * t + 1] = s1;
-                }
-            }
-        }
-        __syncthreads();   // LDS is reused by the next item's prologue
-    }
-}
-
 }  // namespace
 
 // Persistent schedule for a split square on n_p: G = CUs x workgroups per CU (a multiple
 // of 8, at most kMaxSkGrid), R whole rounds, and the leftover tiles cut into s = G / rem
 // K-chunks.  Returns false when there are fewer tiles than workgroups.
-bool square_sk_plan(int tile, int np, int cus, int* wg_per_cu, StreamK* sk, int* T, int* ntiles) {
+bool square_sk_plan(int tile, int variant, int np, int cus, int* wg_per_cu, StreamK* sk, int* T, int* ntiles) {
+    const SkVariant* V = sk_variant(tile, variant);
+    if (!V) return false;
     *T = np / tile;
     *ntiles = ntiles_upper(*T);
-    const int per_cu = tile == 256 ? 1 : 2;   // LDS: 4 slices of 32 KB or 16 KB per workgroup
+    const int lds = V->stages * 4 * tile * V->sk * 2;
+    int per_cu = (160 * 1024) / lds;
+    if (tile == 256 || per_cu < 1) per_cu = 1;   // 256 tiles: the accumulators fill the register file
+    if (per_cu > 2) per_cu = 2;
     int g = cus * per_cu;
     if (g > kMaxSkGrid) g = kMaxSkGrid;
     g -= g % 8;
     if (g < 8 || *ntiles < g) return false;
-    const int KS = np / kSK;
+    const int KS = np / V->sk;
+    const int Q = V->sk >= 32 ? 1 : 2;   // tail chunks are cut on groups of Q slices
     sk->grid = g;
     sk->rounds = *ntiles / g;
     sk->tail_tiles = *ntiles % g;
     sk->chunks = sk->tail_tiles ? g / sk->tail_tiles : 1;
-    if (sk->chunks > KS) sk->chunks = KS;
+    if (sk->chunks > KS / Q) sk->chunks = KS / Q;
     *wg_per_cu = per_cu;
     return true;
 }
@@ -422,25 +57,11 @@ size_t square_sk_partial_bytes(int tile, int np) {
     return (size_t)kMaxSkGrid * tile * tile * sizeof(float);
 }
 
-hipError_t launch_square_sk(int precision, int tile, int waves, const SquareArgs& a, const StreamK& sk,
+hipError_t launch_square_sk(int precision, int tile, int variant, const SquareArgs& a, const StreamK& sk,
                             hipStream_t s) {
-#define SP2_L(T16, WM, WN, MB, NB) \
-    hipLaunchKernelGGL((k_square_sk<T16, WM, WN, MB, NB>), dim3(sk.grid), dim3(64 * WM * WN), 0, s, a, sk)
-    if (precision == SP2_FP16X2) {
-        if (tile == 256 && waves == 8) SP2_L(_Float16, 2, 4, 4, 2);
-        else if (tile == 256) SP2_L(_Float16, 2, 2, 4, 4);
-        else if (tile == 128) SP2_L(_Float16, 2, 2, 2, 2);
-        else return hipErrorInvalidValue;
-    } else if (precision == SP2_BF16X2) {
-        if (tile == 256 && waves == 8) SP2_L(__bf16, 2, 4, 4, 2);
-        else if (tile == 256) SP2_L(__bf16, 2, 2, 4, 4);
-        else if (tile == 128) SP2_L(__bf16, 2, 2, 2, 2);
-        else return hipErrorInvalidValue;
-    } else {
-        return hipErrorInvalidValue;
-    }
-#undef SP2_L
-    return hipGetLastError();
+    if (precision == SP2_FP16X2) return launch_sk_t<_Float16>(tile, variant, a, sk, s);
+    if (precision == SP2_BF16X2) return launch_sk_t<__bf16>(tile, variant, a, sk, s);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace sp2

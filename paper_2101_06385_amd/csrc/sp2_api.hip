@@ -21,6 +21,7 @@ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 struct Opts {
     int precision, max_layers, have_bounds, refine, scale_log2, want_energy, tile, kernel;
+    int tile_ref;   // FP64 refinement tile, 0 = by size (set only by the batched path)
     double eps, emin, emax;
 };
 
@@ -35,6 +36,7 @@ bool read_opts(const sp2_options* o, Opts* r) {
     r->want_energy = o->want_energy;
     r->tile = o->tile;
     r->kernel = o->kernel;
+    r->tile_ref = 0;
     r->eps = o->eps;
     r->emin = o->emin;
     r->emax = o->emax;
@@ -46,8 +48,7 @@ bool read_opts(const sp2_options* o, Opts* r) {
     if (r->max_layers < 1 || r->max_layers >= SP2_MAX_LAYERS) return false;
     if (r->tile != 0 && r->tile != 64 && r->tile != 128 && r->tile != 256) return false;
     if (r->tile == 256 && !split) return false;
-    if (r->kernel < 0 || r->kernel > 3) return false;
-    if (r->kernel == 3 && r->tile != 0 && r->tile != 256) return false;
+    if (r->kernel < 0 || r->kernel > 1 + kSkVariants) return false;
     if (!isfinite(r->eps)) return false;
     if (r->have_bounds && !(isfinite(r->emin) && isfinite(r->emax) && r->emax > r->emin)) return false;
     return true;
@@ -57,31 +58,34 @@ struct Plan {
     int n, np, precision, tile_main, tile_ref, scale_log2;
     bool split;
     int init_tiles, main_T, main_tiles, main_per, ref_T, ref_tiles, ref_per, gersh_blocks, dstats_blocks;
-    int kernel;       // resolved request: 1 = one workgroup per tile, 2/3 = stream-K (4/8 waves)
+    int kernel;       // request: 0 = automatic, 1 = one workgroup per tile, 2.. = persistent variant - 2
     bool sk_capable;  // stream-K buffers are part of the workspace
     size_t off_init_parts, off_main_parts, off_gersh, off_dstats, off_s[2], off_p[2][2], off_s64, off_y;
     size_t off_sk_partial, off_sk_counter, total;
 };
 
-// Stream-K needs a tile of 128 or 256 in a split mode; kernel 1 asks for the
-// one-workgroup-per-tile schedule.  The automatic choice takes stream-K for 256 tiles
-// only: with 128 tiles two one-tile workgroups per CU measured faster than stream-K.
+// The persistent (whole rounds + split tail) schedule needs a tile of 128 or 256 in a
+// split mode; kernel 1 asks for the one-workgroup-per-tile schedule.  The automatic
+// choice takes the persistent schedule for 256 tiles only: with 128 tiles two one-tile
+// workgroups per CU measured faster.
 bool sk_wanted(bool split, int tile, int kernel) {
     if (!split || tile < 128 || kernel == 1) return false;
     return kernel != 0 || tile == 256;
 }
 
+// Persistent variant used when the caller leaves the choice open (index into the
+// per-tile variant table of the kernel): the fastest measured on MI355X.
+int sk_auto_variant(int tile) { return tile == 256 ? 1 : 0; }
+
 // Resolves the squaring schedule for this device; false = one workgroup per tile.
-bool sk_resolve(const Plan& p, StreamK* sk, int* waves) {
+bool sk_resolve(const Plan& p, StreamK* sk, int* variant) {
     if (!p.sk_capable) return false;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return false;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
     int per_cu = 0, T = 0, nt = 0;
-    const int tile_for_plan = p.tile_main;
-    if (!square_sk_plan(tile_for_plan, p.np, cus, &per_cu, sk, &T, &nt)) return false;
-    *waves = (p.kernel == 3 && p.tile_main == 256) ? 8 : 4;
-    return true;
+    *variant = p.kernel >= 2 ? p.kernel - 2 : sk_auto_variant(p.tile_main);
+    return square_sk_plan(p.tile_main, *variant, p.np, cus, &per_cu, sk, &T, &nt);
 }
 
 int auto_tile_main(int n, bool split) {
@@ -97,7 +101,7 @@ void make_plan(int n, const Opts& o, Plan* p) {
     p->split = o.precision == SP2_FP16X2 || o.precision == SP2_BF16X2;
     p->scale_log2 = o.scale_log2;
     p->tile_main = o.tile ? o.tile : auto_tile_main(n, p->split);
-    p->tile_ref = n <= 512 ? 64 : 128;
+    p->tile_ref = o.tile_ref ? o.tile_ref : (n <= 512 ? 64 : 128);
     const int m = p->tile_main > p->tile_ref ? p->tile_main : p->tile_ref;
     p->np = round_up(n, m);
     p->init_tiles = init_tiles(p->np);
@@ -292,6 +296,40 @@ size_t sp2_workspace_size(int n, const sp2_options* opt) {
     return p.total;
 }
 
+static DevState initial_state(int n, int n_occ, double tol, const Opts& o, const Plan& p) {
+    DevState init;
+    memset(&init, 0, sizeof(init));
+    init.n = n;
+    init.n_occ = n_occ;
+    init.n_padded = p.np;
+    init.max_layers = o.max_layers;
+    init.precision = o.precision;
+    init.tile = p.tile_main;
+    init.have_bounds = o.have_bounds;
+    init.want_energy = o.want_energy;
+    init.eps = o.eps;
+    init.tol_tr = tol > 0 ? tol : 1e-6;
+    init.tol_id = tol > 0 ? tol : 1e-6 * n;
+    init.emin = o.have_bounds ? o.emin : 0.0;
+    init.emax = o.have_bounds ? o.emax : 1.0;
+    init.status = SP2_OK;
+    return init;
+}
+
+// Occupation 0 or n: D = 0 or I is fixed by the occupation alone; the state (already
+// initialised at the start of ws) records a converged call of 0 layers.
+static hipError_t run_trivial(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ, const Opts& o,
+                       const Plan& p, char* ws, hipStream_t s) {
+    DevState* st = (DevState*)ws;
+    double* dstats = (double*)(ws + p.off_dstats);
+    hipError_t e = launch_fill(dD, ldd, n, n_occ == n ? 1.0 : 0.0, s);
+    int nd = 0;
+    if (e == hipSuccess) e = launch_dstats(dD, ldd, o.want_energy ? dH : nullptr, ldh, n, dstats, &nd, s);
+    if (e == hipSuccess) e = launch_mark_trivial(st, s);
+    if (e == hipSuccess) e = launch_finalize(st, dstats, nd, (const double*)(ws + p.off_init_parts), 0, s);
+    return e;
+}
+
 static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ, double tol,
                        const sp2_options* opt, sp2_info* info, void* dWork, size_t work_bytes, void* stream,
                        sp2_timing* timing) {
@@ -310,35 +348,16 @@ static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, in
     if (!ev.ok) return SP2_EDEVICE;
     SP2_TRY(ev.rec(ev.start, s));
 
-    DevState init;
-    memset(&init, 0, sizeof(init));
-    init.n = n;
-    init.n_occ = n_occ;
-    init.n_padded = p.np;
-    init.max_layers = o.max_layers;
-    init.precision = o.precision;
-    init.tile = p.tile_main;
-    init.have_bounds = o.have_bounds;
-    init.want_energy = o.want_energy;
-    init.eps = o.eps;
-    init.tol_tr = tol > 0 ? tol : 1e-6;
-    init.tol_id = tol > 0 ? tol : 1e-6 * n;
-    init.emin = o.have_bounds ? o.emin : 0.0;
-    init.emax = o.have_bounds ? o.emax : 1.0;
+    const DevState init = initial_state(n, n_occ, tol, o, p);
     SP2_TRY(launch_state_init(st, init, s));
 
     double* init_parts = (double*)(ws + p.off_init_parts);
     double* main_parts = (double*)(ws + p.off_main_parts);
-    double* dstats = (double*)(ws + p.off_dstats);
 
     if (n_occ == 0 || n_occ == n) {
-        // D = 0 or I: the projector is fixed by the occupation alone
-        SP2_TRY(launch_fill(dD, ldd, n, n_occ == n ? 1.0 : 0.0, s));
-        int nd = 0;
-        SP2_TRY(launch_dstats(dD, ldd, o.want_energy ? dH : nullptr, ldh, n, dstats, &nd, s));
-        SP2_TRY(launch_mark_trivial(st, s));
-        SP2_TRY(launch_finalize(st, dstats, nd, init_parts, 0, s));
+        SP2_TRY(run_trivial(dH, ldh, dD, ldd, n, n_occ, o, p, ws, s));
     } else {
+        double* dstats = (double*)(ws + p.off_dstats);
         if (!o.have_bounds) {
             int nb = 0;
             double* gersh = (double*)(ws + p.off_gersh);
@@ -353,8 +372,8 @@ static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, in
 
         StreamK sk;
         memset(&sk, 0, sizeof(sk));
-        int sk_waves = 4;
-        const bool use_sk = sk_resolve(p, &sk, &sk_waves);
+        int sk_variant = 0;
+        const bool use_sk = sk_resolve(p, &sk, &sk_variant);
         if (use_sk) {
             sk.partial = (float*)(ws + p.off_sk_partial);
             sk.counter = (int*)(ws + p.off_sk_counter);
@@ -409,7 +428,7 @@ static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, in
             ev.launched = layer;
             SP2_TRY(ev.rec(ev.sq_b[layer], s));
             if (use_sk)
-                SP2_TRY(launch_square_sk(o.precision, p.tile_main, sk_waves, a, sk, s));
+                SP2_TRY(launch_square_sk(o.precision, p.tile_main, sk_variant, a, sk, s));
             else if (p.split)
                 SP2_TRY(launch_square_split(o.precision, p.tile_main, a, s));
             else
@@ -527,7 +546,7 @@ int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int ker
     if (precision < SP2_FP64 || precision > SP2_BF16X2) return SP2_EINVAL;
     const bool split = precision == SP2_FP16X2 || precision == SP2_BF16X2;
     if (tile != 0 && tile != 64 && tile != 128 && !(tile == 256 && split)) return SP2_EINVAL;
-    if (kernel < 0 || kernel > 3) return SP2_EINVAL;
+    if (kernel < 0 || kernel > 1 + kSkVariants) return SP2_EINVAL;
     if (scale_log2 < 0) scale_log2 = precision == SP2_FP16X2 ? 12 : 0;
     if (!split) scale_log2 = 0;
     if (scale_log2 > (precision == SP2_FP16X2 ? 14 : 60)) return SP2_EINVAL;
@@ -576,13 +595,13 @@ int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int ker
         pl.sk_capable = sk_wanted(true, t, kernel);
         StreamK sk;
         memset(&sk, 0, sizeof(sk));
-        int waves = 4;
-        if (sk_resolve(pl, &sk, &waves)) {
+        int variant = 0;
+        if (sk_resolve(pl, &sk, &variant)) {
             sk.partial = (float*)(ws + off);
             off = align_up(off + square_sk_partial_bytes(t, np));
             sk.counter = (int*)(ws + off);
             SP2_TRY(launch_zero_ints(sk.counter, kMaxSkGrid, s));
-            SP2_TRY(launch_square_sk(precision, t, waves, a, sk, s));
+            SP2_TRY(launch_square_sk(precision, t, variant, a, sk, s));
         } else {
             SP2_TRY(launch_square_split(precision, t, a, s));
         }
@@ -611,8 +630,8 @@ struct BatchLayout {
     std::vector<int> nontrivial;        // indices of problems that run the recursion
     std::vector<Plan> plans;
     std::vector<size_t> region;         // byte offset of each problem's region
-    size_t off_probs, off_sq, off_offs, off_states, total;
-    int n_offs;                         // entries per offset array (nontrivial + 1)
+    size_t off_probs, off_sq, off_offs, total;
+    int n_offs;                         // stride of the offset arrays (batch + 1)
 };
 
 bool batch_layout(int batch, const int* n, const int* n_occ, const Opts& o, BatchLayout* L) {
@@ -627,20 +646,21 @@ bool batch_layout(int batch, const int* n, const int* n_occ, const Opts& o, Batc
     for (int i = 0; i < batch; ++i) {
         Opts oi = o;
         oi.tile = L->tile;
-        oi.kernel = 1;   // one workgroup per tile: grouped launches
+        oi.tile_ref = L->tile;   // one refinement tile for every problem of the grouped launch
+        oi.kernel = 1;           // one workgroup per tile: grouped launches
         make_plan(n[i], oi, &L->plans[i]);
         if (n_occ && n_occ[i] > 0 && n_occ[i] < n[i]) L->nontrivial.push_back(i);
     }
-    const int nt = (int)L->nontrivial.size();
-    L->n_offs = nt + 1;
+    // descriptor areas are sized for every problem, so the size does not depend on n_occ
+    L->n_offs = batch + 1;
     size_t off = 0;
     L->off_probs = off;
-    off = align_up(off + sizeof(BatchProblem) * (nt ? nt : 1));
+    off = align_up(off + sizeof(BatchProblem) * batch);
     L->off_sq = off;
-    off = align_up(off + sizeof(SquareArgs) * 4 * (nt ? nt : 1));   // even layer, odd layer, refine 1, refine 2
+    off = align_up(off + sizeof(SquareArgs) * 4 * batch);   // even layer, odd layer, refine 1, refine 2
     L->off_offs = off;
-    off = align_up(off + sizeof(int) * 5 * L->n_offs);               // gersh, init, main, ref, dstats
-    L->off_states = off;   // (unused: each problem's state sits at the start of its region)
+    off = align_up(off + sizeof(int) * 5 * L->n_offs);      // gersh, init, main, ref, dstats
+    // then one single-problem region per problem; its DevState sits at the region's start
     for (int i = 0; i < batch; ++i) {
         L->region[i] = off;
         off = align_up(off + L->plans[i].total);
@@ -653,6 +673,7 @@ bool batch_opts(const sp2_options* opt, Opts* o) {
     if (!read_opts(opt, o)) return false;
     if (o->precision == SP2_FP64) return false;   // the batched path keeps FP32 state
     if (o->have_bounds) return false;             // per-problem Gershgorin bounds only
+    o->refine = 1;                                // the batched sequence always refines
     return true;
 }
 
@@ -684,18 +705,12 @@ int sp2_density_batched(int batch, const double* const* dH, const int* ldh, doub
     if (work_bytes < L.total) return SP2_ENOMEM;
     char* ws = (char*)dWork;
     hipStream_t user = (hipStream_t)stream;
-    sp2_options opt1;
-    if (opt) opt1 = *opt;
-    else sp2_default_options(&opt1);
-    opt1.tile = L.tile;
-    opt1.kernel = 1;
-
-    // problems with an empty or full occupation: D = 0 or I, through the single path
+    // problems with an empty or full occupation: D = 0 or I, on the caller's stream
     for (int i = 0; i < batch; ++i) {
         if (n_occ[i] > 0 && n_occ[i] < n[i]) continue;
-        const int st = sp2_density(dH[i], ldh[i], dD[i], ldd[i], n[i], n_occ[i], tol, &opt1, nullptr,
-                                   ws + L.region[i], L.plans[i].total, stream);
-        if (st != SP2_OK) return st;
+        char* r = ws + L.region[i];
+        SP2_TRY(launch_state_init((DevState*)r, initial_state(n[i], n_occ[i], tol, o, L.plans[i]), user));
+        SP2_TRY(run_trivial(dH[i], ldh[i], dD[i], ldd[i], n[i], n_occ[i], o, L.plans[i], r, user));
     }
     const int nt = (int)L.nontrivial.size();
     if (nt > 0) {
@@ -784,21 +799,7 @@ int sp2_density_batched(int batch, const double* const* dH, const int* ldh, doub
                 a.ntiles = p.ref_tiles;
                 a.per = p.ref_per;
             }
-            DevState& s0 = states[k];
-            memset(&s0, 0, sizeof(s0));
-            s0.n = n[i];
-            s0.n_occ = n_occ[i];
-            s0.n_padded = p.np;
-            s0.max_layers = o.max_layers;
-            s0.precision = o.precision;
-            s0.tile = p.tile_main;
-            s0.want_energy = o.want_energy;
-            s0.eps = o.eps;
-            s0.tol_tr = tol > 0 ? tol : 1e-6;
-            s0.tol_id = tol > 0 ? tol : 1e-6 * n[i];
-            s0.emin = 0.0;
-            s0.emax = 1.0;
-            s0.status = SP2_OK;
+            states[k] = initial_state(n[i], n_occ[i], tol, o, p);
         }
         // uploads (synchronous, before anything of this call is enqueued)
         SP2_TRY(hipStreamSynchronize(user));
@@ -832,10 +833,8 @@ int sp2_density_batched(int batch, const double* const* dH, const int* ldh, doub
                     SP2_TRY(launch_square_split_g(o.precision, L.tile, a, d_om, nt, o_m[nt], s));
             }
             SP2_TRY(launch_batch_select(d_probs, nt, 64, s));
-            SP2_TRY(launch_square_plain_g(SP2_FP64, L.plans[L.nontrivial[0]].tile_ref, d_sq + 2 * nt, d_or, nt,
-                                          o_r[nt], s));
-            SP2_TRY(launch_square_plain_g(SP2_FP64, L.plans[L.nontrivial[0]].tile_ref, d_sq + 3 * nt, d_or, nt,
-                                          o_r[nt], s));
+            SP2_TRY(launch_square_plain_g(SP2_FP64, L.tile, d_sq + 2 * nt, d_or, nt, o_r[nt], s));
+            SP2_TRY(launch_square_plain_g(SP2_FP64, L.tile, d_sq + 3 * nt, d_or, nt, o_r[nt], s));
             SP2_TRY(launch_batch_dstats(d_probs, d_od, nt, o_d[nt], s));
             SP2_TRY(launch_batch_finalize(d_probs, nt, s));
             return SP2_OK;

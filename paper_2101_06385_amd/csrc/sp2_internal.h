@@ -121,6 +121,7 @@ struct SquareArgs {
 // `partial` holds one FP32 tile accumulator per tail chunk, `counter` one arrival count
 // per tail tile (zeroed at the start of every call; each executed layer adds `chunks`).
 constexpr int kMaxSkGrid = 1024;
+constexpr int kSkVariants = 4;
 struct StreamK {
     int grid, rounds, tail_tiles, chunks;
     float* partial;
@@ -180,9 +181,10 @@ hipError_t launch_square_plain_g(int precision, int tile, const SquareArgs* desc
                                  int blocks, hipStream_t s);
 int square_split_grid(int tile, int np, int* T, int* ntiles, int* per);
 int square_plain_grid(int tile, int np, int* T, int* ntiles, int* per);
-bool square_sk_plan(int tile, int np, int cus, int* wg_per_cu, StreamK* sk, int* T, int* ntiles);
+// persistent split square: kSkVariants kernel variants per tile edge (128, 256)
+bool square_sk_plan(int tile, int variant, int np, int cus, int* wg_per_cu, StreamK* sk, int* T, int* ntiles);
 size_t square_sk_partial_bytes(int tile, int np);
-hipError_t launch_square_sk(int precision, int tile, int waves, const SquareArgs& a, const StreamK& sk,
+hipError_t launch_square_sk(int precision, int tile, int variant, const SquareArgs& a, const StreamK& sk,
                             hipStream_t s);
 hipError_t launch_zero_ints(int* p, int count, hipStream_t s);
 

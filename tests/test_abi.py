@@ -84,8 +84,9 @@ def test_invalid_options_give_zero_workspace():
     assert sp2.workspace_size(100, sp2.options(precision="fp64", tile=256)) == 0
     assert sp2.workspace_size(100, sp2.options(bounds=(1.0, -1.0))) == 0
     assert sp2.workspace_size(100, sp2.options(precision="fp16x2", scale_log2=15)) == 0
-    assert sp2.workspace_size(100, sp2.options(kernel=4)) == 0
-    assert sp2.workspace_size(100, sp2.options(kernel=3, tile=128)) == 0
+    assert sp2.workspace_size(100, sp2.options(kernel=6)) == 0
+    assert sp2.workspace_size(100, sp2.options(kernel=-1)) == 0
+    assert sp2.workspace_size(100, sp2.options(kernel=5, tile=128)) > 0
 
 
 def test_argument_errors_return_before_device_work():
@@ -132,8 +133,8 @@ def test_batched_workspace_and_argument_errors():
     o = sp2.options()
     sizes = [64, 130, 700]
     total = sp2.batched_workspace_size(sizes, o)
-    singles = sum(sp2.workspace_size(n, sp2.options(tile=64, kernel=1)) for n in sizes)
-    assert total >= singles
+    # per problem at least two FP32 state matrices, four half planes and two FP64 refinement buffers
+    assert total >= sum(n * n * (2 * 4 + 4 * 2 + 2 * 8) for n in sizes)
     assert sp2.batched_workspace_size([], o) == 0
     assert sp2.batched_workspace_size([0, 10], o) == 0
     assert sp2.batched_workspace_size(sizes, sp2.options(precision="fp64")) == 0

@@ -79,12 +79,14 @@ def test_plain_square_vs_fp64(prec, tile, n):
 
 
 @pytest.mark.parametrize("prec,tile,kernel,n", [
-    ("fp16x2", 256, 2, 6100), ("fp16x2", 256, 3, 6100), ("fp16x2", 128, 2, 4100), ("bf16x2", 256, 2, 6100),
-    ("fp16x2", 256, 1, 6100),
+    ("fp16x2", 256, 2, 6100), ("fp16x2", 256, 3, 6100), ("fp16x2", 256, 4, 6100), ("fp16x2", 256, 5, 6100),
+    ("fp16x2", 128, 2, 4100), ("fp16x2", 128, 3, 4100), ("fp16x2", 128, 4, 4100), ("fp16x2", 128, 5, 4100),
+    ("bf16x2", 256, 3, 6100), ("bf16x2", 128, 3, 4100), ("fp16x2", 256, 1, 6100),
 ])
 def test_persistent_schedules_sampled_rows(prec, tile, kernel, n):
-    """Stream-K schedules (only used once there are at least as many tiles as
-    workgroups, hence the large n): sampled rows against the oracle's exact products."""
+    """Persistent schedules, every kernel variant (only used once there are at least as
+    many tiles as workgroups, hence the large n; 300 and 561 tiles leave a split tail):
+    sampled rows against the oracle's exact products."""
     fmt = "fp16" if prec == "fp16x2" else "bf16"
     s = 12 if fmt == "fp16" else 0
     rng = np.random.default_rng(n + kernel)
