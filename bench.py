@@ -5,14 +5,20 @@ One step is one call of the whole path through the C ABI (sp2_density): Gershgor
 bounds, input layer, the Alg. 1 layers with the dual-FP16 squaring of Alg. 2, the FP64
 refinement layer and the final checks, on the N = 8192 small-gap stress Hamiltonian
 (25% occupation, 0.2 eV gap, eigenvalues uniform in [-25, 25] eV) resident in HBM.
+The timed steps use the event-instrumented entry point (same kernels, HIP events
+recorded between them on the library's stream), so the per-kernel durations below
+come from the timed steps themselves.
 
 Reported (one JSON line on stdout; progress on stderr):
-  value            executed MFMA TFLOP/s of the layer loop: (m - 1) squarings x 3 N^2 (N + 1)
-                   FLOP (three half-precision products over the upper triangle) divided by
-                   the loop time measured with HIP events (the paper's rate also leaves out
-                   set-up and the refinement layer)
+  value            whole-call throughput: FLOP executed per call (every squaring layer,
+                   3 N^2 (N + 1) for the three half-precision products over the upper
+                   triangle, plus the two FP64 refinement products, N^2 (N + 1) each)
+                   divided by the time-to-D of the call
   ms_per_step      time-to-D of one full call, H resident on the device
-  roofline         the squaring kernel against the dense FP16 matrix peak
+  loop_tflops      squaring layers only (executed FLOP), over the loop time
+  paper_convention_tflops  the paper's accounting: 4 N^3 per mixed layer (two dense
+                   half-precision products), loop time only, no set-up or refinement
+  roofline         the squaring kernel (dominant) against the dense FP16 matrix peak
   fp64             the same computation with FP64 squarings on the GPU (speed comparison)
   accuracy         ||D - D_ref||_F and |Tr D - N_occ| with D_ref the exact projector
   cpu_baseline     the CPU oracle (FP64 NumPy Alg. 1) on a bounded sample of the workload
@@ -45,6 +51,59 @@ def flop_split_layer(n):
 def flop_plain_layer(n):
     """One FP32/FP64 product restricted to the upper triangle (with diagonal)."""
     return 2.0 * n * (n * (n + 1) / 2.0)
+
+
+# Persistent-kernel variants (waves, K-slice halves, LDS stages, L2 prefetch distance) per
+# tile edge, in the order of the library's kernel option 2..7.
+SK_VARIANTS = {256: [(4, 16, 4, 0), (8, 16, 4, 0), (4, 32, 2, 0), (8, 32, 2, 0), (4, 32, 2, 4), (8, 32, 2, 4)],
+               128: [(4, 32, 4, 0), (4, 64, 2, 0), (4, 16, 4, 0), (4, 32, 2, 0), (4, 64, 2, 2), (4, 32, 2, 4)]}
+
+
+def kernel_name(precision, tile, kernel):
+    """Name of the squaring kernel a call used (as reported in sp2_info.kernel)."""
+    if precision in ("fp16x2", "bf16x2"):
+        t16 = "_Float16" if precision == "fp16x2" else "__bf16"
+        if kernel >= 2:
+            waves, sk, st, pf = SK_VARIANTS[tile][kernel - 2]
+            wn = waves // 2
+            mb = tile // 64
+            nb = tile // (32 * wn)
+            return "k_square_sk<%s, 2, %d, %d, %d, %d, %d, %d>" % (t16, wn, mb, nb, sk, st, pf)
+        return "k_square_split<%s, %d>" % (t16, tile)
+    return "k_square_plain<%s, %d>" % ("double" if precision == "fp64" else "float", tile)
+
+
+def kernel_sources_digest():
+    """SHA-256 over the sources of the squaring kernels: counter records taken with other
+    sources no longer describe the kernel."""
+    import glob
+    import hashlib
+
+    hsh = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2101_06385_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "k_square*")) + glob.glob(os.path.join(csrc, "k_sk_*")) +
+                    [os.path.join(csrc, "sp2_internal.h")]):
+        hsh.update(os.path.basename(f).encode())
+        hsh.update(open(f, "rb").read())
+    return hsh.hexdigest()
+
+
+def recorded_traffic(kname, n):
+    """HBM bytes per launch of `kname` at size n from profiles/traffic.json (rocprofv3 FETCH_SIZE
+    and WRITE_SIZE, FETCH scaled by the copy-kernel calibration), or None when no record
+    matches this kernel, size and source digest."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        recs = json.load(open(path))
+    except ValueError:
+        return None
+    dig = kernel_sources_digest()
+    for r in recs.get("records", []):
+        if r.get("kernel") == kname and int(r.get("n", 0)) == n and r.get("sources_sha256") == dig:
+            return float(r["hbm_bytes_per_launch"])
+    return None
 
 
 def main():
@@ -85,33 +144,38 @@ def main():
     torch.cuda.synchronize()
 
     def step():
-        sp2.density(h, w.n_occ, precision=args.precision, out=d, workspace=ws)
+        return sp2.density(h, w.n_occ, precision=args.precision, out=d, workspace=ws, timed=True)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    steps = []
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        steps.append(step())
     torch.cuda.synchronize()
     ms_per_step = (time.perf_counter() - t_start) * 1e3 / args.steps
     log("time-to-D %.2f ms per step" % ms_per_step)
 
-    # one more call with HIP events between the kernels: loop time and squaring kernel time
-    _, info, tm = sp2.density(h, w.n_occ, precision=args.precision, out=d, workspace=ws, timed=True)
+    _, info, tm = steps[-1]
+    split = args.precision in ("fp16x2", "bf16x2")
+    f_layer = flop_split_layer(n) if split else flop_plain_layer(n)
+    f_refine = 2 * flop_plain_layer(n)
     k = tm["squarings"]
-    sq = [t for t in tm["square_ms"][:k]]
-    f_layer = flop_split_layer(n) if args.precision in ("fp16x2", "bf16x2") else flop_plain_layer(n)
-    loop_ms = tm["loop_active_ms"]
-    value = k * f_layer / (loop_ms * 1e-3) / 1e12
-    paper_rate = k * (4.0 if args.precision in ("fp16x2", "bf16x2") else 2.0) * n ** 3 / (loop_ms * 1e-3) / 1e12
+    flop_call = k * f_layer + f_refine
+    value = flop_call / (ms_per_step * 1e-3) / 1e12
+    loop_ms = float(np.mean([t["loop_active_ms"] for _, _, t in steps]))
+    loop_tflops = k * f_layer / (loop_ms * 1e-3) / 1e12
+    sq = [x for _, _, t in steps for x in t["square_ms"][:t["squarings"]]]
     sq_mean = float(np.mean(sq)) if sq else float("nan")
     achieved = f_layer / (sq_mean * 1e-3) / 1e12
-    peak = PEAK_FP16_TFLOPS if args.precision in ("fp16x2", "bf16x2") else (
-        PEAK_FP64_TFLOPS if args.precision == "fp64" else 157.3)
-    log("layers m=%d squarings=%d loop %.2f ms (%.1f TFLOP/s) square kernel %.3f ms (%.1f TFLOP/s) "
-        "refine %.2f ms status %s" % (info["layers"], k, loop_ms, value, sq_mean, achieved, tm["refine_ms"],
-                                       info["status_name"]))
+    peak = PEAK_FP16_TFLOPS if split else (PEAK_FP64_TFLOPS if args.precision == "fp64" else 157.3)
+    kname = kernel_name(args.precision, info["tile"], info["kernel"])
+    traffic = recorded_traffic(kname, n)
+    log("layers m=%d squarings=%d loop %.2f ms (%.1f TFLOP/s) square kernel %.3f ms (%.1f TFLOP/s, %s) "
+        "refine %.2f ms status %s; whole call %.1f TFLOP/s" % (info["layers"], k, loop_ms, loop_tflops, sq_mean,
+                                                              achieved, kname, tm["refine_ms"],
+                                                              info["status_name"], value))
 
     out = {
         "metric": METRIC,
@@ -134,18 +198,20 @@ def main():
             "layers": info["layers"], "squarings": k, "tile": info["tile"], "n_padded": info["n_padded"],
         },
         "time_to_d_ms": round(ms_per_step, 3),
+        "flop_per_call": flop_call,
+        "loop_tflops": round(loop_tflops, 3),
+        "paper_convention_tflops": round(k * (4.0 if split else 2.0) * n ** 3 / (loop_ms * 1e-3) / 1e12, 3),
         "loop_ms": round(loop_ms, 3),
-        "refine_ms": round(tm["refine_ms"], 3),
-        "prep_ms": round(tm["prep_ms"], 3),
-        "paper_convention_tflops": round(paper_rate, 3),
+        "refine_ms": round(float(np.mean([t["refine_ms"] for _, _, t in steps])), 3),
+        "prep_ms": round(float(np.mean([t["prep_ms"] for _, _, t in steps])), 3),
         "status": info["status_name"],
         "trace_error": abs(info["trace"] - w.n_occ),
         "idempotency": info["idem"],
         "roofline": {
             "bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None,
-            "kernel": "k_square_split<_Float16,256,2,4>" if n > 2048 and args.precision == "fp16x2" else "square",
-            "flop_per_launch": f_layer, "launch_ms": round(sq_mean, 4),
+            "frac": round(achieved / peak, 4), "traffic": traffic,
+            "kernel": kname, "flop_per_launch": f_layer, "launch_ms": round(sq_mean, 4),
+            "launches_timed": len(sq),
         },
     }
 
@@ -181,7 +247,7 @@ def main():
             cores = max([p.get("num_threads", 0) for p in threadpool_info()] + [1])
         except Exception:  # pragma: no cover
             cores = os.cpu_count()
-        layers = 2
+        layers = 10
         tc = time.perf_counter()
         osp2.sp2_alg1(w.h, w.n_occ, max_layers=layers, refine=False)
         tcpu = time.perf_counter() - tc

@@ -72,11 +72,11 @@ typedef struct {
     int want_energy;   /* nonzero: info->energy = Tr[D H] (the observable of Alg. 1) */
     int tile;          /* output tile edge of the squaring kernels: 0 = automatic, or 64/128/256 */
     int kernel;        /* split-mode squaring schedule: 0 = automatic, 1 = one workgroup per
-                          tile, 2..5 = persistent schedule (whole rounds of tiles, then the
-                          leftover tiles split along K), kernel variant 0..3 for the tile:
-                            256: (4 waves, 16-half K-slices, 4 LDS stages), (8, 16, 4),
-                                 (4, 32, 2), (8, 32, 2)
-                            128: (4, 32, 4), (4, 64, 2), (4, 16, 4), (4, 32, 2)
+                          tile, 2..7 = persistent schedule (whole rounds of tiles, then the
+                          leftover tiles split along K), kernel variant 0..5 for the tile,
+                          as (waves, K-slice halves, LDS stages, L2 prefetch distance):
+                            256: (4,16,4,0) (8,16,4,0) (4,32,2,0) (8,32,2,0) (4,32,2,4) (8,32,2,4)
+                            128: (4,32,4,0) (4,64,2,0) (4,16,4,0) (4,32,2,0) (4,64,2,2) (4,32,2,4)
                           Only split modes with tiles of 128/256 use it; otherwise ignored. */
 } sp2_options;
 
@@ -87,6 +87,9 @@ typedef struct {
     int first_sign;        /* sign of the first of the two composed refinement steps */
     int n_padded;          /* internal matrix edge (n rounded up to the tile) */
     int tile;              /* output tile edge used */
+    int kernel;            /* squaring schedule used: 1 = one workgroup per tile (also every
+                              FP32/FP64 run), 2 + v = persistent schedule, variant v */
+    int reserved;
     double emin, emax;     /* spectral bounds used */
     double trace;          /* Tr D */
     double idem;           /* Tr D - ||D||_F^2  (= Tr[D - D^2] for symmetric D) */

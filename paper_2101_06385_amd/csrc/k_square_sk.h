@@ -84,18 +84,24 @@ __device__ inline double wsum(double v) {
 // s_waitcnt needs an immediate: wait until at most n vector-memory instructions of this
 // wavefront are outstanding, for the counts the pipeline below can ask for.
 #define SP2_VMCNT(n) asm volatile("s_waitcnt vmcnt(" #n ")" ::: "memory")
+// Rounds n down to an immediate it has (waiting for more than asked is always safe).
 __device__ __forceinline__ void wait_vm(int n) {
-    switch (n) {
-        case 48: SP2_VMCNT(48); break;
-        case 40: SP2_VMCNT(40); break;
-        case 32: SP2_VMCNT(32); break;
-        case 24: SP2_VMCNT(24); break;
-        case 16: SP2_VMCNT(16); break;
-        case 12: SP2_VMCNT(12); break;
-        case 8: SP2_VMCNT(8); break;
-        case 4: SP2_VMCNT(4); break;
-        default: SP2_VMCNT(0); break;   // also every count not listed: wait for all
-    }
+    if (n >= 48) SP2_VMCNT(48);
+    else if (n >= 40) SP2_VMCNT(40);
+    else if (n >= 32) SP2_VMCNT(32);
+    else if (n >= 28) SP2_VMCNT(28);
+    else if (n >= 24) SP2_VMCNT(24);
+    else if (n >= 20) SP2_VMCNT(20);
+    else if (n >= 18) SP2_VMCNT(18);
+    else if (n >= 16) SP2_VMCNT(16);
+    else if (n >= 14) SP2_VMCNT(14);
+    else if (n >= 12) SP2_VMCNT(12);
+    else if (n >= 10) SP2_VMCNT(10);
+    else if (n >= 8) SP2_VMCNT(8);
+    else if (n >= 6) SP2_VMCNT(6);
+    else if (n >= 4) SP2_VMCNT(4);
+    else if (n >= 2) SP2_VMCNT(2);
+    else SP2_VMCNT(0);
 }
 #undef SP2_VMCNT
 
@@ -108,6 +114,17 @@ typedef __attribute__((address_space(3))) unsigned char lds_byte;
 __device__ __forceinline__ unsigned lds_addr(const unsigned char* p) {
     return (unsigned)(uintptr_t)(const lds_byte*)p;
 }
+// L2 prefetch of one 128-byte line per lane: a 4-byte direct load into a scratch LDS word
+// that nothing reads (no VGPR is written, so no register can be clobbered late).
+__device__ __forceinline__ void touch4(const void* g, unsigned lds_base) {
+    asm volatile(
+        "s_mov_b32 m0, %1\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dword %0, off"
+        :
+        : "v"(g), "s"(lds_base)
+        : "memory", "m0");
+}
 __device__ __forceinline__ void dma16(const void* g, unsigned lds_base) {
     asm volatile(
         "s_mov_b32 m0, %1\n\t"
@@ -118,7 +135,7 @@ __device__ __forceinline__ void dma16(const void* g, unsigned lds_base) {
         : "memory", "m0");
 }
 
-template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST>
+template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST, int PF>
 struct Cfg {
     static constexpr int NW = WM * WN;
     static constexpr int NT = 64 * NW;
@@ -136,13 +153,16 @@ struct Cfg {
     static constexpr int BPR = BT / RPB;           // 1 KB blocks per panel slice
     static constexpr int LPW = 4 * BPR / NW;       // direct-load instructions per wave per slice
     static_assert((4 * BPR) % NW == 0, "slice blocks must split evenly over waves");
-    static_assert(LDS <= 160 * 1024, "LDS budget");
+    static constexpr int LINE = SK >= 64 ? 1 : 64 / SK;   // slices per 128-byte line of a row
+    static constexpr int PFI = 4 * BT / NT;        // prefetch instructions per wave per line group
+    static constexpr int LDS_ALL = LDS + (PF ? 256 : 0);
+    static_assert(LDS_ALL <= 160 * 1024, "LDS budget");
     static_assert(LPW * (ST - 1) <= 48, "vmcnt range of wait_vm");
 };
 
-template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST>
+template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST, int PF>
 __global__ __launch_bounds__(64 * WM * WN) void k_square_sk(SquareArgs a, StreamK sk) {
-    typedef Cfg<T16, WM, WN, MB, NB, SK, ST> C;
+    typedef Cfg<T16, WM, WN, MB, NB, SK, ST, PF> C;
     typedef typename H2<T16>::vec8 vec8;
     typedef typename H2<T16>::vec4 vec4;
     constexpr int BT = C::BT;
@@ -150,7 +170,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_sk(SquareArgs a, Stream
     constexpr int ROW = C::ROW;
     constexpr int UPS = C::UPS;
 
-    __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS];
+    __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS_ALL];
     __shared__ int s_flag;
 
     if (a.skip && *a.skip) return;
@@ -193,6 +213,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_sk(SquareArgs a, Stream
             kb = Q * (int)(((long long)chunk * (KS / Q)) / sk.chunks);
             ke = Q * (int)(((long long)(chunk + 1) * (KS / Q)) / sk.chunks);
         }
+        const int nsl = ke - kb;   // slices of this work item
         int I, J;
         tile_of(t, a.T, 8, &I, &J);
         const T16* src[4] = {x0 + (size_t)I * BT * np, x1 + (size_t)I * BT * np, x0 + (size_t)J * BT * np,
@@ -208,6 +229,21 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_sk(SquareArgs a, Stream
                 const T16* g = src[arr] + (size_t)row * np + ks * SK + ((lpc ^ swz<C::CPR>(row)) << 3);
                 dma16(g, __builtin_amdgcn_readfirstlane(
                              lds_addr(lds + buf * C::STAGE + arr * C::ARR + qd * 1024)));
+            }
+        };
+        // L2 prefetch of the 128-byte lines holding slice p (relative to kb) of the four
+        // panels, when p starts a line; returns the vector-memory instructions issued
+        auto pf_ops = [&](int p) -> int {
+            return (PF > 0 && p < nsl && (kb + p) % C::LINE == 0) ? C::PFI : 0;
+        };
+        auto prefetch = [&](int p) {
+            if (pf_ops(p) == 0) return;
+            const unsigned scratch = __builtin_amdgcn_readfirstlane(lds_addr(lds + C::LDS));
+#pragma unroll
+            for (int i = 0; i < C::PFI; ++i) {
+                const int q = tid + i * C::NT;
+                const int arr = q / BT, row = q % BT;
+                touch4(src[arr] + (size_t)row * np + (kb + p) * SK, scratch);
             }
         };
         // fragments of unit u (0 <= u < UPS) of the slice in buffer buf
@@ -254,11 +290,22 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_sk(SquareArgs a, Stream
         // ---------------------------------------------------------------- main loop
         // slice kb + j lives in LDS buffer j % ST.  Prologue: the first ST slices in
         // flight, the first one landed and its first unit read into fragment set P.
+        // Slice q is issued (with the prefetch of slice q + PF right after it) by
+        // advance(q - ST + 1); the prologue plays the advances of slices 0 .. ST - 1.
+        // To wait for slice t, a wave allows the vector-memory instructions it issued
+        // after slice t to stay outstanding (they complete in order).
         wait_vm(0);   // nothing of the previous item may still count against vmcnt
-        const int nsl = ke - kb;
         const int pro = nsl < ST ? nsl : ST;
-        for (int q = 0; q < pro; ++q) issue(q, kb + q);
-        wait_vm((pro - 1) * LPW);   // the first slice has landed
+        for (int q = 0; q < pro; ++q) {
+            issue(q, kb + q);
+            prefetch(q + PF);
+        }
+        auto after = [&](int tslice, int last_issued) {
+            int c = pf_ops(tslice + PF);
+            for (int q = tslice + 1; q <= last_issued; ++q) c += LPW + pf_ops(q + PF);
+            return c;
+        };
+        wait_vm(after(0, pro - 1));   // the first slice has landed
         __syncthreads();
         vec8 pa0[MB], pa1[MB], pb0[NB], pb1[NB];   // fragments of even units
         vec8 qa0[MB], qa1[MB], qb0[NB], qb1[NB];   // fragments of odd units
@@ -268,11 +315,17 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_sk(SquareArgs a, Stream
         // that buffer with slice next + ST - 1.  Invariant on entry: slices up to
         // next + ST - 2 have been issued.  The caller then reads `next`'s fragments.
         auto advance = [&](int next) {
-            const int issued = (next + ST - 1 < nsl) ? next + ST - 1 : nsl;   // slices issued so far
-            const int later = issued - (next + 1);
-            wait_vm((later > 0 ? later : 0) * LPW);
+            const int last = (next + ST - 2 < nsl - 1) ? next + ST - 2 : nsl - 1;   // last slice issued
+            if constexpr (PF == 0) {
+                wait_vm((last - next) * LPW);
+            } else {
+                wait_vm(after(next, last));
+            }
             __syncthreads();
-            if (next + ST - 1 < nsl) issue((next - 1) % ST, kb + next + ST - 1);
+            if (next + ST - 1 < nsl) {
+                issue((next - 1) % ST, kb + next + ST - 1);
+                prefetch(next + ST - 1 + PF);
+            }
         };
         // Units run in pairs (P, Q); unit w is unit w % UPS of slice w / UPS.  Each step
         // reads the next unit's fragments while the matrix cores work on the current one.
@@ -463,22 +516,28 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_sk(SquareArgs a, Stream
 
 template <typename T16>
 hipError_t launch_sk_t(int tile, int variant, const SquareArgs& a, const StreamK& sk, hipStream_t s) {
-#define SP2_L(WM, WN, MB, NB, SK, ST) \
-    hipLaunchKernelGGL((k_square_sk<T16, WM, WN, MB, NB, SK, ST>), dim3(sk.grid), dim3(64 * WM * WN), 0, s, a, sk)
+#define SP2_L(WM, WN, MB, NB, SK, ST, PF)                                                            \
+    hipLaunchKernelGGL((k_square_sk<T16, WM, WN, MB, NB, SK, ST, PF>), dim3(sk.grid), dim3(64 * WM * WN), 0, \
+                       s, a, sk)
+    // variant tables: keep in step with kV256 / kV128 in k_square2.hip
     if (tile == 256) {
         switch (variant) {
-            case 0: SP2_L(2, 2, 4, 4, 16, 4); break;
-            case 1: SP2_L(2, 4, 4, 2, 16, 4); break;
-            case 2: SP2_L(2, 2, 4, 4, 32, 2); break;
-            case 3: SP2_L(2, 4, 4, 2, 32, 2); break;
+            case 0: SP2_L(2, 2, 4, 4, 16, 4, 0); break;
+            case 1: SP2_L(2, 4, 4, 2, 16, 4, 0); break;
+            case 2: SP2_L(2, 2, 4, 4, 32, 2, 0); break;
+            case 3: SP2_L(2, 4, 4, 2, 32, 2, 0); break;
+            case 4: SP2_L(2, 2, 4, 4, 32, 2, 4); break;
+            case 5: SP2_L(2, 4, 4, 2, 32, 2, 4); break;
             default: return hipErrorInvalidValue;
         }
     } else if (tile == 128) {
         switch (variant) {
-            case 0: SP2_L(2, 2, 2, 2, 32, 4); break;
-            case 1: SP2_L(2, 2, 2, 2, 64, 2); break;
-            case 2: SP2_L(2, 2, 2, 2, 16, 4); break;
-            case 3: SP2_L(2, 2, 2, 2, 32, 2); break;
+            case 0: SP2_L(2, 2, 2, 2, 32, 4, 0); break;
+            case 1: SP2_L(2, 2, 2, 2, 64, 2, 0); break;
+            case 2: SP2_L(2, 2, 2, 2, 16, 4, 0); break;
+            case 3: SP2_L(2, 2, 2, 2, 32, 2, 0); break;
+            case 4: SP2_L(2, 2, 2, 2, 64, 2, 2); break;
+            case 5: SP2_L(2, 2, 2, 2, 32, 2, 4); break;
             default: return hipErrorInvalidValue;
         }
     } else {

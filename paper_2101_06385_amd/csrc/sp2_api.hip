@@ -74,8 +74,14 @@ bool sk_wanted(bool split, int tile, int kernel) {
 }
 
 // Persistent variant used when the caller leaves the choice open (index into the
-// per-tile variant table of the kernel): the fastest measured on MI355X.
-int sk_auto_variant(int tile) { return tile == 256 ? 1 : 0; }
+// per-tile variant table of the kernel), the fastest measured on MI355X: for 256 tiles
+// 8 waves with 32-half slices up to n_p = 12288 (871 TFLOP/s at 8192), 4 waves above
+// (844 TFLOP/s at 16384, where the 8-wave variant reached 803); for 128 tiles the
+// 64-half slices.
+int sk_auto_variant(int tile, int np) {
+    if (tile == 256) return np <= 12288 ? 3 : 2;
+    return 1;
+}
 
 // Resolves the squaring schedule for this device; false = one workgroup per tile.
 bool sk_resolve(const Plan& p, StreamK* sk, int* variant) {
@@ -84,7 +90,7 @@ bool sk_resolve(const Plan& p, StreamK* sk, int* variant) {
     if (hipGetDevice(&dev) != hipSuccess) return false;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
     int per_cu = 0, T = 0, nt = 0;
-    *variant = p.kernel >= 2 ? p.kernel - 2 : sk_auto_variant(p.tile_main);
+    *variant = p.kernel >= 2 ? p.kernel - 2 : sk_auto_variant(p.tile_main, p.np);
     return square_sk_plan(p.tile_main, *variant, p.np, cus, &per_cu, sk, &T, &nt);
 }
 
@@ -165,7 +171,11 @@ void fill_info(const DevState& st, const Plan* p, sp2_info* info) {
         info->ns[k - 1] = st.ns[k];
         info->nx[k - 1] = st.nx[k];
     }
-    (void)p;
+    if (p) {
+        StreamK sk;
+        int variant = 0;
+        info->kernel = sk_resolve(*p, &sk, &variant) ? 2 + variant : 1;
+    }
 }
 
 #define SP2_TRY(expr)                                   \

@@ -121,7 +121,7 @@ struct SquareArgs {
 // `partial` holds one FP32 tile accumulator per tail chunk, `counter` one arrival count
 // per tail tile (zeroed at the start of every call; each executed layer adds `chunks`).
 constexpr int kMaxSkGrid = 1024;
-constexpr int kSkVariants = 4;
+constexpr int kSkVariants = 6;
 struct StreamK {
     int grid, rounds, tail_tiles, chunks;
     float* partial;

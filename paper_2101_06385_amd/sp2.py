@@ -46,6 +46,8 @@ class Info(ctypes.Structure):
         ("first_sign", ctypes.c_int),
         ("n_padded", ctypes.c_int),
         ("tile", ctypes.c_int),
+        ("kernel", ctypes.c_int),
+        ("reserved", ctypes.c_int),
         ("emin", ctypes.c_double),
         ("emax", ctypes.c_double),
         ("trace", ctypes.c_double),
@@ -193,6 +195,7 @@ def info_dict(info: Info) -> dict:
         "first_sign": int(info.first_sign),
         "n_padded": int(info.n_padded),
         "tile": int(info.tile),
+        "kernel": int(info.kernel),
         "emin": float(info.emin),
         "emax": float(info.emax),
         "trace": float(info.trace),

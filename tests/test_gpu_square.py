@@ -81,7 +81,8 @@ def test_plain_square_vs_fp64(prec, tile, n):
 @pytest.mark.parametrize("prec,tile,kernel,n", [
     ("fp16x2", 256, 2, 6100), ("fp16x2", 256, 3, 6100), ("fp16x2", 256, 4, 6100), ("fp16x2", 256, 5, 6100),
     ("fp16x2", 128, 2, 4100), ("fp16x2", 128, 3, 4100), ("fp16x2", 128, 4, 4100), ("fp16x2", 128, 5, 4100),
-    ("bf16x2", 256, 3, 6100), ("bf16x2", 128, 3, 4100), ("fp16x2", 256, 1, 6100),
+    ("fp16x2", 256, 6, 6100), ("fp16x2", 256, 7, 6100), ("fp16x2", 128, 6, 4100), ("fp16x2", 128, 7, 4100),
+    ("bf16x2", 256, 3, 6100), ("bf16x2", 128, 3, 4100), ("bf16x2", 256, 7, 6100), ("fp16x2", 256, 1, 6100),
 ])
 def test_persistent_schedules_sampled_rows(prec, tile, kernel, n):
     """Persistent schedules, every kernel variant (only used once there are at least as
