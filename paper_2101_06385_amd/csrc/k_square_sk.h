@@ -290,8 +290,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_sk(SquareArgs a, Stream
         // ---------------------------------------------------------------- main loop
         // slice kb + j lives in LDS buffer j % ST.  Prologue: the first ST slices in
         // flight, the first one landed and its first unit read into fragment set P.
-        // Slice q is issued (with the prefetch of slice q + PF right after it) by
-        // advance(q - ST + 1); the prologue plays the advances of slices 0 .. ST - 1.
+        // Slice q is issued (with the prefetch of slice q + PF right after it) among the
+        // MFMAs that follow arrive(q - ST + 1); the prologue issues slices 0 .. ST - 1.
         // To wait for slice t, a wave allows the vector-memory instructions it issued
         // after slice t to stay outstanding (they complete in order).
         wait_vm(0);   // nothing of the previous item may still count against vmcnt
@@ -314,7 +314,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_sk(SquareArgs a, Stream
         // the buffer of slice next - 1, already read into registers, is free) and refill
         // that buffer with slice next + ST - 1.  Invariant on entry: slices up to
         // next + ST - 2 have been issued.  The caller then reads `next`'s fragments.
-        auto advance = [&](int next) {
+        // Make slice `next` readable: its loads landed (the ones this wave issued; all
+        // later ones may stay in flight) and every wave is past the barrier, so the buffer
+        // of slice next - 1, already read into registers, is free.
+        auto arrive = [&](int next) {
             const int last = (next + ST - 2 < nsl - 1) ? next + ST - 2 : nsl - 1;   // last slice issued
             if constexpr (PF == 0) {
                 wait_vm((last - next) * LPW);
@@ -322,10 +325,48 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_sk(SquareArgs a, Stream
                 wait_vm(after(next, last));
             }
             __syncthreads();
-            if (next + ST - 1 < nsl) {
-                issue((next - 1) % ST, kb + next + ST - 1);
-                prefetch(next + ST - 1 + PF);
+        };
+        // The MFMAs of one unit with the direct loads that refill the buffer freed by
+        // arrive(next) (slice next + ST - 1) spread between the X0 X0 and X0 X1 products, so
+        // that their address arithmetic and issue overlap the matrix cores (scheduling
+        // barriers keep the compiler from regrouping them), then `mid` (the fragment reads of
+        // the next unit: by then the X0 fragments of this unit and its X1 column fragments
+        // are dead, which keeps the register count down), then the X1 X0 products.  Last,
+        // the L2 prefetch of slice next + ST - 1 + PF.
+        auto mma_issue = [&](const vec8 (&fa0)[MB], const vec8 (&fa1)[MB], const vec8 (&fb0)[NB],
+                             const vec8 (&fb1)[NB], int next, auto&& mid) {
+            constexpr int NM = 2 * MB * NB;
+            const bool doit = next + ST - 1 < nsl;
+            const int buf = (next - 1) % ST, ks = kb + next + ST - 1;
+#pragma unroll
+            for (int i = 0; i < NM; ++i) {
+                const int m = (i / NB) % MB, n = i % NB;
+                acc[m][n] = H2<T16>::mfma(fa0[m], i < MB * NB ? fb0[n] : fb1[n], acc[m][n]);
+                // the loads l with ceil(l NM / LPW) == i go right after MFMA i
+                const int l0 = (i * LPW + NM - 1) / NM, l1 = ((i + 1) * LPW + NM - 1) / NM;
+                if (l1 > l0) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (doit) {
+#pragma unroll
+                        for (int l = l0; l < l1; ++l) {
+                            const int j = wave * LPW + l;
+                            const int arr = j / C::BPR;
+                            const int qd = j % C::BPR;
+                            const int row = qd * C::RPB + lrow;
+                            const T16* g = src[arr] + (size_t)row * np + ks * SK + ((lpc ^ swz<C::CPR>(row)) << 3);
+                            dma16(g, __builtin_amdgcn_readfirstlane(
+                                         lds_addr(lds + buf * C::STAGE + arr * C::ARR + qd * 1024)));
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             }
+            mid();
+#pragma unroll
+            for (int m = 0; m < MB; ++m)
+#pragma unroll
+                for (int n = 0; n < NB; ++n) acc[m][n] = H2<T16>::mfma(fa1[m], fb0[n], acc[m][n]);
+            if (doit) prefetch(next + ST - 1 + PF);
         };
         // Units run in pairs (P, Q); unit w is unit w % UPS of slice w / UPS.  Each step
         // reads the next unit's fragments while the matrix cores work on the current one.
@@ -335,26 +376,31 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_sk(SquareArgs a, Stream
         int w = 0;
         for (; w + 2 < nu; w += 2) {
             if constexpr (UPS == 1) {
-                advance(w + 1);
-                frags((w + 1) % ST, 0, qa0, qa1, qb0, qb1);
+                arrive(w + 1);
+                mma_issue(pa0, pa1, pb0, pb1, w + 1, [&] { frags((w + 1) % ST, 0, qa0, qa1, qb0, qb1); });
+                arrive(w + 2);
+                mma_issue(qa0, qa1, qb0, qb1, w + 2, [&] { frags((w + 2) % ST, 0, pa0, pa1, pb0, pb1); });
+            } else if constexpr (UPS == 2) {
+                frags((w / 2) % ST, 1, qa0, qa1, qb0, qb1);
+                mma(pa0, pa1, pb0, pb1);
+                arrive((w + 2) / 2);
+                mma_issue(qa0, qa1, qb0, qb1, (w + 2) / 2,
+                          [&] { frags(((w + 2) / 2) % ST, 0, pa0, pa1, pb0, pb1); });
             } else {
                 frags((w / UPS) % ST, (w + 1) % UPS, qa0, qa1, qb0, qb1);
+                mma(pa0, pa1, pb0, pb1);
+                if ((w + 2) % UPS == 0) {
+                    arrive((w + 2) / UPS);
+                    mma_issue(qa0, qa1, qb0, qb1, (w + 2) / UPS,
+                              [&] { frags(((w + 2) / UPS) % ST, 0, pa0, pa1, pb0, pb1); });
+                } else {
+                    frags(((w + 2) / UPS) % ST, (w + 2) % UPS, pa0, pa1, pb0, pb1);
+                    mma(qa0, qa1, qb0, qb1);
+                }
             }
-            mma(pa0, pa1, pb0, pb1);
-            if constexpr (UPS == 1) {
-                advance(w + 2);
-                frags((w + 2) % ST, 0, pa0, pa1, pb0, pb1);
-            } else if constexpr (UPS == 2) {
-                advance((w + 2) / 2);
-                frags(((w + 2) / 2) % ST, 0, pa0, pa1, pb0, pb1);
-            } else {
-                if ((w + 2) % UPS == 0) advance((w + 2) / UPS);
-                frags(((w + 2) / UPS) % ST, (w + 2) % UPS, pa0, pa1, pb0, pb1);
-            }
-            mma(qa0, qa1, qb0, qb1);
         }
         if constexpr (UPS == 1) {
-            advance(w + 1);
+            arrive(w + 1);
             frags((w + 1) % ST, 0, qa0, qa1, qb0, qb1);
         } else {
             frags((w / UPS) % ST, (w + 1) % UPS, qa0, qa1, qb0, qb1);

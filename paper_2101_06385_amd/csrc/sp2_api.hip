@@ -49,6 +49,7 @@ bool read_opts(const sp2_options* o, Opts* r) {
     if (r->tile != 0 && r->tile != 64 && r->tile != 128 && r->tile != 256) return false;
     if (r->tile == 256 && !split) return false;
     if (r->kernel < 0 || r->kernel > 1 + kSkVariants) return false;
+    if (r->precision == SP2_FP64 && r->kernel > 4) return false;
     if (!isfinite(r->eps)) return false;
     if (r->have_bounds && !(isfinite(r->emin) && isfinite(r->emax) && r->emax > r->emin)) return false;
     return true;
@@ -92,6 +93,14 @@ bool sk_resolve(const Plan& p, StreamK* sk, int* variant) {
     int per_cu = 0, T = 0, nt = 0;
     *variant = p.kernel >= 2 ? p.kernel - 2 : sk_auto_variant(p.tile_main, p.np);
     return square_sk_plan(p.tile_main, *variant, p.np, cus, &per_cu, sk, &T, &nt);
+}
+
+// FP64 layer: the direct-load kernel on 128 tiles (kernel 2 / 3 / 4 = its variants 0 / 1 /
+// 2, 0 = automatic), the register-staged plain kernel for 64 tiles or kernel 1.
+constexpr int kF64AutoVariant = 2;
+hipError_t launch_f64_layer(int tile, int kernel, const SquareArgs& a, hipStream_t s) {
+    if (tile == 128 && kernel != 1) return launch_square_f64(kernel >= 2 ? kernel - 2 : kF64AutoVariant, a, s);
+    return launch_square_plain(SP2_FP64, tile, a, s);
 }
 
 int auto_tile_main(int n, bool split) {
@@ -441,6 +450,8 @@ static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, in
                 SP2_TRY(launch_square_sk(o.precision, p.tile_main, sk_variant, a, sk, s));
             else if (p.split)
                 SP2_TRY(launch_square_split(o.precision, p.tile_main, a, s));
+            else if (o.precision == SP2_FP64)
+                SP2_TRY(launch_f64_layer(p.tile_main, o.kernel, a, s));
             else
                 SP2_TRY(launch_square_plain(o.precision, p.tile_main, a, s));
             SP2_TRY(ev.rec(ev.sq_e[layer], s));
@@ -465,7 +476,7 @@ static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, in
             r.n_valid = p.np;
             r.n_real = n;
             r.coef = st->rcoef[0];
-            SP2_TRY(launch_square_plain(SP2_FP64, p.tile_ref, r, s));
+            SP2_TRY(launch_f64_layer(p.tile_ref, o.precision == SP2_FP64 ? o.kernel : 0, r, s));
             SP2_TRY(ev.rec(ev.ref[1], s));
             r.x0 = y;
             r.s_in = y;
@@ -473,7 +484,7 @@ static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, in
             r.ld_out = ldd;
             r.n_valid = n;
             r.coef = st->rcoef[1];
-            SP2_TRY(launch_square_plain(SP2_FP64, p.tile_ref, r, s));
+            SP2_TRY(launch_f64_layer(p.tile_ref, o.precision == SP2_FP64 ? o.kernel : 0, r, s));
             SP2_TRY(ev.rec(ev.ref[2], s));
         } else {
             SP2_TRY(launch_select_f64(st, S[0], S[1], o.precision == SP2_FP64, dD, ldd, n, p.np, s));
@@ -557,6 +568,7 @@ int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int ker
     const bool split = precision == SP2_FP16X2 || precision == SP2_BF16X2;
     if (tile != 0 && tile != 64 && tile != 128 && !(tile == 256 && split)) return SP2_EINVAL;
     if (kernel < 0 || kernel > 1 + kSkVariants) return SP2_EINVAL;
+    if (precision == SP2_FP64 && kernel > 4) return SP2_EINVAL;
     if (scale_log2 < 0) scale_log2 = precision == SP2_FP16X2 ? 12 : 0;
     if (!split) scale_log2 = 0;
     if (scale_log2 > (precision == SP2_FP16X2 ? 14 : 60)) return SP2_EINVAL;
@@ -615,6 +627,9 @@ int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int ker
         } else {
             SP2_TRY(launch_square_split(precision, t, a, s));
         }
+    } else if (precision == SP2_FP64) {
+        a.x0 = dX;
+        SP2_TRY(launch_f64_layer(t, kernel, a, s));
     } else {
         a.x0 = dX;
         SP2_TRY(launch_square_plain(precision, t, a, s));

@@ -175,6 +175,8 @@ hipError_t launch_batch_finalize(const BatchProblem* pr, int nprob, hipStream_t 
 // Host-side launchers (defined next to their kernels).
 hipError_t launch_square_split(int precision, int tile, const SquareArgs& a, hipStream_t s);
 hipError_t launch_square_plain(int precision, int tile, const SquareArgs& a, hipStream_t s);
+// FP64 layer with direct-to-LDS staging, 128 tiles (k_square_f64.hip); variant 0 or 1
+hipError_t launch_square_f64(int variant, const SquareArgs& a, hipStream_t s);
 hipError_t launch_square_split_g(int precision, int tile, const SquareArgs* descs, const int* offs, int nprob,
                                  int blocks, hipStream_t s);
 hipError_t launch_square_plain_g(int precision, int tile, const SquareArgs* descs, const int* offs, int nprob,

@@ -138,3 +138,24 @@ def test_square_is_deterministic():
     y1, s1 = sp2.square(x, precision="fp16x2", tile=256)
     y2, s2 = sp2.square(x, precision="fp16x2", tile=256)
     assert torch.equal(y1, y2) and s1 == s2
+
+
+@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4])
+def test_fp64_kernels_vs_exact(kernel):
+    """The FP64 layer kernels (register-staged, direct-to-LDS variants) on a
+    ragged size that spans several 128 tiles: each within the FP64 accumulation bound of
+    the exact product, all bitwise symmetric."""
+    n = 900
+    x = _state(n, 300)
+    x2 = x @ x
+    mag = np.abs(x) @ np.abs(x)
+    u = 2.0 ** -53
+    for alpha, beta, gamma in COEFS:
+        y, sums = sp2.square(torch.from_numpy(x).to(DEV), alpha, beta, gamma, precision="fp64", tile=128,
+                             kernel=kernel)
+        y = y.cpu().numpy()
+        assert np.array_equal(y, y.T)
+        ref = alpha * x2 + beta * x + gamma * np.eye(n)
+        bound = 2.0 * n * u * mag * abs(alpha) + 2.0 * u * (np.abs(alpha * x2) + abs(beta) * np.abs(x) + abs(gamma))
+        assert np.all(np.abs(y - ref) <= bound + 1e-300), kernel
+        _check_sums(y, sums)
