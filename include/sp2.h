@@ -208,6 +208,37 @@ int sp2_density_batched(int batch, const double* const* dH, const int* ldh, doub
                         size_t work_bytes, void* stream);
 
 /*
+ * Autotuner.  The automatic choices of sp2_density (tile = 0 and kernel = 0) and of
+ * sp2_density_batched (tile = 0) come from a built-in rule unless the autotuner has
+ * measured this case on the current device in this process; then its fastest choice is
+ * used.  Tune before sizing workspaces: the workspace depends on the schedule.
+ *
+ * sp2_autotune -- for an n x n split-precision problem (SP2_FP16X2 or SP2_BF16X2): times
+ *   one squaring layer of a synthetic symmetric matrix (reps launches after a warm-up,
+ *   HIP events on `stream`) for every schedule that can run at this size (tiles 64/128/256,
+ *   one workgroup per tile or a persistent variant, as the kernel option numbers them),
+ *   records the fastest for sizes that round up to the same multiple of 256, and returns
+ *   it in *tile, *kernel, *ms (host pointers, each may be NULL).  Synchronizes `stream`.
+ *   dWork: sp2_autotune_workspace_size(n, precision) bytes, 256-byte aligned; its contents
+ *   are overwritten.  Errors: SP2_EINVAL (bad n, precision, reps outside 1..1000, NULL or
+ *   misaligned dWork), SP2_ENOMEM, SP2_EDEVICE; argument errors return before any work.
+ * sp2_autotune_batched -- runs sp2_density_batched on these problems (same arguments; D is
+ *   written) once per grouped-kernel tile (64, 128), twice each, timed on the host, and
+ *   records the faster tile for this multiset of sizes.  dWork:
+ *   sp2_autotune_batched_workspace_size() bytes.
+ * sp2_autotune_reset -- forgets every measurement (built-in rules again).
+ * The table is process-wide and guarded by a mutex.
+ */
+size_t sp2_autotune_workspace_size(int n, int precision);
+int sp2_autotune(int n, int precision, int reps, int* tile, int* kernel, float* ms, void* dWork,
+                 size_t work_bytes, void* stream);
+size_t sp2_autotune_batched_workspace_size(int batch, const int* n, const sp2_options* opt);
+int sp2_autotune_batched(int batch, const double* const* dH, const int* ldh, double* const* dD,
+                         const int* ldd, const int* n, const int* n_occ, const sp2_options* opt,
+                         int* tile, float* ms, void* dWork, size_t work_bytes, void* stream);
+void sp2_autotune_reset(void);
+
+/*
  * Differentiable generalized-SP2 network (Eq. general SP2 applied to matrices):
  *
  *     X_{k+1} = W_k X_k^2 + B_k X_k + c_k I,     k = 0 .. K-1

@@ -115,7 +115,16 @@ void make_plan(int n, const Opts& o, Plan* p) {
     p->precision = o.precision;
     p->split = o.precision == SP2_FP16X2 || o.precision == SP2_BF16X2;
     p->scale_log2 = o.scale_log2;
-    p->tile_main = o.tile ? o.tile : auto_tile_main(n, p->split);
+    // automatic schedule: the autotuner's measurement for this size class if there is one
+    int tile = o.tile, kernel = o.kernel;
+    if (p->split && tile == 0 && kernel == 0) {
+        int tt = 0, kk = 0;
+        if (tune_lookup(kTuneSingle, o.precision, tune_key_single(n), &tt, &kk)) {
+            tile = tt;
+            kernel = kk;
+        }
+    }
+    p->tile_main = tile ? tile : auto_tile_main(n, p->split);
     p->tile_ref = o.tile_ref ? o.tile_ref : (n <= 512 ? 64 : 128);
     const int m = p->tile_main > p->tile_ref ? p->tile_main : p->tile_ref;
     p->np = round_up(n, m);
@@ -151,8 +160,8 @@ void make_plan(int n, const Opts& o, Plan* p) {
     off = align_up(off + (o.refine ? 8 * np2 : 0));
     p->off_y = off;
     off = align_up(off + (o.refine ? 8 * np2 : 0));
-    p->kernel = o.kernel;
-    p->sk_capable = sk_wanted(p->split, p->tile_main, o.kernel);
+    p->kernel = kernel;
+    p->sk_capable = sk_wanted(p->split, p->tile_main, kernel);
     p->off_sk_partial = off;
     if (p->sk_capable) off = align_up(off + square_sk_partial_bytes(p->tile_main, p->np));
     p->off_sk_counter = off;
@@ -663,7 +672,11 @@ bool batch_layout(int batch, const int* n, const int* n_occ, const Opts& o, Batc
     L->batch = batch;
     int nmin = 1 << 30;
     for (int i = 0; i < batch; ++i) nmin = n[i] < nmin ? n[i] : nmin;
-    L->tile = o.tile ? o.tile : (nmin <= 256 ? 64 : 128);
+    int tuned = 0, tuned_kernel = 0;
+    if (o.tile == 0 && tune_lookup(kTuneBatched, o.precision, tune_key_batched(batch, n), &tuned, &tuned_kernel))
+        L->tile = tuned;
+    else
+        L->tile = o.tile ? o.tile : (nmin <= 256 ? 64 : 128);
     if (L->tile == 256) L->tile = 128;
     L->plans.resize(batch);
     L->region.resize(batch);

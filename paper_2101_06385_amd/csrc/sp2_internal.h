@@ -122,6 +122,15 @@ struct SquareArgs {
 // per tail tile (zeroed at the start of every call; each executed layer adds `chunks`).
 constexpr int kMaxSkGrid = 1024;
 constexpr int kSkVariants = 6;
+
+// Autotuner table (sp2_tune.hip): the fastest measured schedule per (device, kind,
+// precision, key); kind single: key = n rounded up to 256; kind batched: key = hash of the
+// sorted sizes.
+constexpr int kTuneSingle = 0, kTuneBatched = 1;
+unsigned long long tune_key_single(int n);
+unsigned long long tune_key_batched(int batch, const int* n);
+bool tune_lookup(int kind, int precision, unsigned long long key, int* tile, int* kernel);
+void tune_store(int kind, int precision, unsigned long long key, int tile, int kernel, float ms);
 struct StreamK {
     int grid, rounds, tail_tiles, chunks;
     float* partial;

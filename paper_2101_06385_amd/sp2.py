@@ -120,6 +120,20 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(c_int), c_double, ctypes.POINTER(Options),
                                       ctypes.POINTER(Info), c_int, c_void_p, c_size_t, c_void_p]
     L.sp2_density_batched.restype = c_int
+    L.sp2_autotune_workspace_size.argtypes = [c_int, c_int]
+    L.sp2_autotune_workspace_size.restype = c_size_t
+    L.sp2_autotune.argtypes = [c_int, c_int, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                               ctypes.POINTER(c_float), c_void_p, c_size_t, c_void_p]
+    L.sp2_autotune.restype = c_int
+    L.sp2_autotune_batched_workspace_size.argtypes = [c_int, ctypes.POINTER(c_int), ctypes.POINTER(Options)]
+    L.sp2_autotune_batched_workspace_size.restype = c_size_t
+    L.sp2_autotune_batched.argtypes = [c_int, ctypes.POINTER(c_void_p), ctypes.POINTER(c_int),
+                                       ctypes.POINTER(c_void_p), ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                                       ctypes.POINTER(c_int), ctypes.POINTER(Options), ctypes.POINTER(c_int),
+                                       ctypes.POINTER(c_float), c_void_p, c_size_t, c_void_p]
+    L.sp2_autotune_batched.restype = c_int
+    L.sp2_autotune_reset.argtypes = []
+    L.sp2_autotune_reset.restype = None
     L.sp2_net_workspace_size.argtypes = [c_int, c_int, c_int, c_int]
     L.sp2_net_workspace_size.restype = c_size_t
     L.sp2_net_forward.argtypes = [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_int, c_int,
@@ -309,6 +323,54 @@ def density_batched(hs, n_occs, tol: float = 0.0, precision="fp16x2", max_layers
     if st in (SP2_EDEVICE, SP2_ENOMEM) or (st == SP2_EINVAL and all(int(i.n_padded) == 0 for i in infos)):
         raise SP2Error(st, "sp2_density_batched")
     return outs, [info_dict(i) for i in infos]
+
+
+def autotune(n: int, precision="fp16x2", reps: int = 3, device="cuda:0", stream=None) -> dict:
+    """Measure every squaring schedule for an n x n problem on `device` and record the
+    fastest for later automatic choices (see sp2_autotune)."""
+    p = _prec(precision)
+    need = int(lib().sp2_autotune_workspace_size(int(n), p))
+    if need == 0:
+        raise SP2Error(SP2_EINVAL, "sp2_autotune_workspace_size")
+    ws = alloc_workspace(need, device)
+    tile, kernel, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_float(0.0)
+    st = lib().sp2_autotune(int(n), p, int(reps), ctypes.byref(tile), ctypes.byref(kernel), ctypes.byref(ms),
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(ws.device, stream))
+    if st != SP2_OK:
+        raise SP2Error(st, "sp2_autotune")
+    return {"tile": tile.value, "kernel": kernel.value, "ms": ms.value}
+
+
+def autotune_batched(hs, n_occs, precision="fp16x2", max_layers=100, stream=None) -> dict:
+    """Time the batched solve of these problems with each grouped-kernel tile and record
+    the faster one for this multiset of sizes (see sp2_autotune_batched)."""
+    import torch
+
+    b = len(hs)
+    opts = options(precision, max_layers)
+    sizes = (ctypes.c_int * b)(*[int(h.shape[0]) for h in hs])
+    need = int(lib().sp2_autotune_batched_workspace_size(b, sizes, ctypes.byref(opts)))
+    if need == 0:
+        raise SP2Error(SP2_EINVAL, "sp2_autotune_batched_workspace_size")
+    dev = hs[0].device
+    ws = alloc_workspace(need, dev)
+    outs = [torch.empty_like(h) for h in hs]
+    ph = (ctypes.c_void_p * b)(*[h.data_ptr() for h in hs])
+    pd = (ctypes.c_void_p * b)(*[d.data_ptr() for d in outs])
+    lh = (ctypes.c_int * b)(*[h.stride(0) for h in hs])
+    ld = (ctypes.c_int * b)(*[d.stride(0) for d in outs])
+    no = (ctypes.c_int * b)(*[int(v) for v in n_occs])
+    tile, ms = ctypes.c_int(0), ctypes.c_float(0.0)
+    st = lib().sp2_autotune_batched(b, ph, lh, pd, ld, sizes, no, ctypes.byref(opts), ctypes.byref(tile),
+                                    ctypes.byref(ms), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                    _stream_ptr(dev, stream))
+    if st != SP2_OK:
+        raise SP2Error(st, "sp2_autotune_batched")
+    return {"tile": tile.value, "ms": ms.value}
+
+
+def autotune_reset() -> None:
+    lib().sp2_autotune_reset()
 
 
 def query(workspace, n, precision="fp16x2", stream=None, device=None, **kw) -> dict:

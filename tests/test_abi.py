@@ -158,3 +158,25 @@ def test_batched_workspace_and_argument_errors():
     assert call(10, 5, 10, 10, work=16) == sp2.SP2_ENOMEM
     assert L.sp2_density_batched(0, ph, I(10), pd, I(10), I(10), I(5), 0.0, ctypes.byref(o), None, 1, fake,
                                  1 << 40, None) == sp2.SP2_EINVAL
+
+
+def test_autotune_sizes_and_argument_errors():
+    L = sp2.lib()
+    assert sp2.lib().sp2_autotune_workspace_size(0, sp2.FP16X2) == 0
+    assert sp2.lib().sp2_autotune_workspace_size(1000, sp2.FP64) == 0
+    w = sp2.lib().sp2_autotune_workspace_size(3000, sp2.FP16X2)
+    assert w >= 2 * 4 * 3072 * 3072
+    fake = ctypes.c_void_p(256)
+    t, k, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+    args = (ctypes.byref(t), ctypes.byref(k), ctypes.byref(ms))
+    assert L.sp2_autotune(0, sp2.FP16X2, 3, *args, fake, 1 << 40, None) == sp2.SP2_EINVAL
+    assert L.sp2_autotune(100, sp2.FP32, 3, *args, fake, 1 << 40, None) == sp2.SP2_EINVAL
+    assert L.sp2_autotune(100, sp2.FP16X2, 0, *args, fake, 1 << 40, None) == sp2.SP2_EINVAL
+    assert L.sp2_autotune(100, sp2.FP16X2, 3, *args, ctypes.c_void_p(260), 1 << 40, None) == sp2.SP2_EINVAL
+    assert L.sp2_autotune(100, sp2.FP16X2, 3, *args, fake, 16, None) == sp2.SP2_ENOMEM
+    sizes = (ctypes.c_int * 3)(256, 512, 640)
+    o = sp2.options()
+    bw = L.sp2_autotune_batched_workspace_size(3, sizes, ctypes.byref(o))
+    o64 = sp2.options(tile=64)
+    assert bw >= sp2.batched_workspace_size([256, 512, 640], o64)
+    L.sp2_autotune_reset()
