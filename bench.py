@@ -116,11 +116,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--gen-device", default="cuda", help="where the QR of the workload generator runs")
+    ap.add_argument("--workload", default="density", choices=["density", "batched", "net"],
+                    help="density: the N=8192 headline (default); batched: 64 Hamiltonians of uneven "
+                         "sizes in one graph; net: the 20-layer differentiable network at N=2048")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the path runs on one MI355X); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "net":
+        return bench_net(args)
 
     import numpy as np
     import torch
@@ -267,6 +274,168 @@ def main():
             acc["fro_error_fp64"] = float(np.linalg.norm(d64.cpu().numpy() - d_ref))
         out["accuracy"] = acc
         log("accuracy: %s" % acc)
+    print(json.dumps(out), flush=True)
+
+
+def _cores():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([p.get("num_threads", 0) for p in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        return os.cpu_count()
+
+
+def bench_batched(args):
+    """64 Hamiltonians, N_i = 64 U{4..48}, occupation U[0.2, 0.5], gap U[0.5, 3] eV, solved by
+    sp2_density_batched (every step one grouped launch, the sequence one hipGraph); compared
+    with the same problems solved one after another by sp2_density."""
+    import numpy as np
+    import torch
+
+    from paper_2101_06385_amd import sp2, workloads
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    ws = workloads.config4(device=None if args.gen_device == "cpu" else "cuda:0")
+    log("64 problems generated in %.1f s" % (time.perf_counter() - t0))
+    hs = [torch.from_numpy(w.h).to(dev) for w in ws]
+    occ = [w.n_occ for w in ws]
+    sizes = [w.n for w in ws]
+    opts = sp2.options(args.precision)
+    wsbuf = sp2.alloc_workspace(sp2.batched_workspace_size(sizes, opts), dev)
+    outs = [torch.empty_like(h) for h in hs]
+
+    def step():
+        return sp2.density_batched(hs, occ, precision=args.precision, outs=outs, workspace=wsbuf)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        _, infos = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) * 1e3 / args.steps
+    split = args.precision in ("fp16x2", "bf16x2")
+    flop = sum((i["layers"] - 1) * (flop_split_layer(n) if split else flop_plain_layer(n)) + 2 * flop_plain_layer(n)
+               for i, n in zip(infos, sizes))
+    value = flop / (ms * 1e-3) / 1e12
+    # the same problems one call at a time (automatic schedule per size)
+    single_ws = sp2.alloc_workspace(max(sp2.workspace_size(n, opts) for n in sizes), dev)
+    for h, o, d in zip(hs, occ, outs):
+        sp2.density(h, o, precision=args.precision, out=d, workspace=single_ws)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for h, o, d in zip(hs, occ, outs):
+        sp2.density(h, o, precision=args.precision, out=d, workspace=single_ws)
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t2) * 1e3
+    _, infos = step()
+    torch.cuda.synchronize()
+    log("batched: %.2f ms per call (%.1f TFLOP/s); one call per problem: %.2f ms" % (ms, value, seq_ms))
+    out = {
+        "metric": "batched SP2 TFLOP/s (64 Hamiltonians of uneven sizes, one graph launch)",
+        "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16" if args.precision == "fp16x2" else args.precision, "data": "synthetic",
+        "config": {"workload": "64 Hamiltonians, N_i = 64*U{4..48} (%d..%d, sum %d), occupation U[0.2,0.5], "
+                               "gap U[0.5,3] eV; Gershgorin bounds" % (min(sizes), max(sizes), sum(sizes)),
+                   "precision": args.precision, "tile": infos[0]["tile"]},
+        "flop_per_call": flop,
+        "layers": {"min": min(i["layers"] for i in infos), "max": max(i["layers"] for i in infos)},
+        "status": sorted(set(i["status_name"] for i in infos)),
+        "sequential_ms": round(seq_ms, 3), "speedup_vs_sequential": round(seq_ms / ms, 3),
+        "roofline": {"bound": "mfma", "achieved": round(value, 3), "peak": PEAK_FP16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(value / PEAK_FP16_TFLOPS, 4), "traffic": None,
+                     "kernel": "whole batched call (grouped squaring kernels dominate)"},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import dm as odm
+        from oracle import sp2 as osp2
+
+        w0 = ws[int(np.argmax(sizes))]
+        tc = time.perf_counter()
+        osp2.sp2_alg1(w0.h, w0.n_occ, max_layers=4, refine=False)
+        tcpu = time.perf_counter() - tc
+        out["cpu_baseline"] = {"value": round(4 * 2.0 * w0.n ** 3 / tcpu / 1e12, 4), "unit": "TFLOP/s",
+                               "cores": int(_cores()), "kind": "oracle",
+                               "sample": "first 4 FP64 layers of Alg. 1 (oracle.sp2.sp2_alg1) on the largest "
+                                         "problem (N=%d), %.1f s; rate credits 2N^3 per layer" % (w0.n, tcpu)}
+        errs = [float(np.linalg.norm(d.cpu().numpy() - odm.dm_construct(w.q, w.eps, w.n_occ))) / np.sqrt(w.n)
+                for w, d in zip(ws, outs)]
+        out["accuracy"] = {"max_fro_error_over_sqrt_n": max(errs), "bound_over_sqrt_n": 1e-3,
+                           "max_trace_error": max(abs(i["trace"] - w.n_occ) for i, w in zip(infos, ws))}
+    print(json.dumps(out), flush=True)
+
+
+def bench_net(args):
+    """The 20-layer network X_{k+1} = W_k X_k^2 + B_k X_k + c_k I at N = 2048 (spectrum
+    U[-15,15] eV, mu = 0, kT = 0.2 eV target): one step = forward (split squarings) +
+    backward (checkpoint recomputation + FP32 adjoint) for the loss ||X_20 - T||_F^2."""
+    import numpy as np
+    import torch
+
+    from paper_2101_06385_amd import sp2, workloads
+
+    dev = torch.device("cuda:0")
+    n, K = 2048, 20
+    w = workloads.config5(device=None if args.gen_device == "cpu" else "cuda:0")
+    # input layer from bounds that enclose the spectrum; alternating SP2 branch coefficients
+    # X^2 and 2X - X^2 (both keep the spectrum in [0, 1])
+    e1, en = float(w.eps.min()) - 0.5, float(w.eps.max()) + 0.5
+    x0 = torch.from_numpy(((en * np.eye(n) - w.h) / (en - e1)).astype(np.float32)).to(dev)
+    coef = [(1.0, 0.0, 0.0) if k % 2 == 0 else (-1.0, 2.0, 0.0) for k in range(K)]
+    wt = torch.tensor([c[0] for c in coef], dtype=torch.float32, device=dev)
+    bt = torch.tensor([c[1] for c in coef], dtype=torch.float32, device=dev)
+    ct = torch.tensor([c[2] for c in coef], dtype=torch.float32, device=dev)
+    q = torch.from_numpy(w.q).to(dev)
+    fd = torch.from_numpy(1.0 / (1.0 + np.exp(w.eps / 0.2))).to(dev)
+    target = ((q * fd) @ q.T).float()
+    wsb = sp2.alloc_workspace(sp2.net_workspace_size(n, K, args.precision), dev)
+
+    def step():
+        xk, _ = sp2.net_forward(x0, wt, bt, ct, precision=args.precision, workspace=wsb)
+        gk = 2.0 * (xk - target)
+        return sp2.net_backward(gk, wt, bt, ct, wsb, precision=args.precision, want_g0=False), xk
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fwd, bwd = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e[0].record()
+        xk, _ = sp2.net_forward(x0, wt, bt, ct, precision=args.precision, workspace=wsb)
+        e[1].record()
+        gk = 2.0 * (xk - target)
+        sp2.net_backward(gk, wt, bt, ct, wsb, precision=args.precision, want_g0=False)
+        e[2].record()
+        torch.cuda.synchronize()
+        fwd.append(e[0].elapsed_time(e[1]))
+        bwd.append(e[1].elapsed_time(e[2]))
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    c = int(math.ceil(math.sqrt(K)))
+    recompute = K - (K + c - 1) // c
+    f_fwd = K * flop_split_layer(n)
+    f_bwd = recompute * flop_split_layer(n) + K * 2 * flop_plain_layer(n)
+    value = (f_fwd + f_bwd) / (ms * 1e-3) / 1e12
+    log("net: step %.2f ms (forward %.2f ms, backward %.2f ms), %.1f TFLOP/s" % (ms, np.mean(fwd), np.mean(bwd), value))
+    out = {
+        "metric": "differentiable SP2 network TFLOP/s (forward + backward, N=2048, 20 layers)",
+        "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16 forward / f32 adjoint", "data": "synthetic",
+        "config": {"workload": "network N=2048, K=20, spectrum U[-15,15] eV, target Fermi-Dirac kT=0.2 eV, "
+                               "checkpoints every %d layers" % c, "precision": args.precision},
+        "forward_ms": round(float(np.mean(fwd)), 3), "backward_ms": round(float(np.mean(bwd)), 3),
+        "forward_tflops": round(f_fwd / (np.mean(fwd) * 1e-3) / 1e12, 3),
+        "backward_tflops": round(f_bwd / (np.mean(bwd) * 1e-3) / 1e12, 3),
+        "roofline": {"bound": "mfma", "achieved": round(f_fwd / (np.mean(fwd) * 1e-3) / 1e12, 3),
+                     "peak": PEAK_FP16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(f_fwd / (np.mean(fwd) * 1e-3) / 1e12 / PEAK_FP16_TFLOPS, 4), "traffic": None,
+                     "kernel": "forward layers (split squaring kernel); the adjoint runs on the FP32 peak 157.3"},
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -72,7 +72,8 @@ typedef struct {
     int want_energy;   /* nonzero: info->energy = Tr[D H] (the observable of Alg. 1) */
     int tile;          /* output tile edge of the squaring kernels: 0 = automatic, or 64/128/256 */
     int kernel;        /* split-mode squaring schedule: 0 = automatic, 1 = one workgroup per
-                          tile, 2..7 = persistent schedule (whole rounds of tiles, then the
+                          tile (direct-to-LDS pipeline for tiles 128/256), 8 = one workgroup
+                          per tile with register staging (every tile), 2..7 = persistent schedule (whole rounds of tiles, then the
                           leftover tiles split along K), kernel variant 0..5 for the tile,
                           as (waves, K-slice halves, LDS stages, L2 prefetch distance):
                             256: (4,16,4,0) (8,16,4,0) (4,32,2,0) (8,32,2,0) (4,32,2,4) (8,32,2,4)
@@ -92,7 +93,8 @@ typedef struct {
     int n_padded;          /* internal matrix edge (n rounded up to the tile) */
     int tile;              /* output tile edge used */
     int kernel;            /* squaring schedule used: 1 = one workgroup per tile (also every
-                              FP32/FP64 run), 2 + v = persistent schedule, variant v */
+                              FP32/FP64 run), 8 = the register-staged per-tile kernel,
+                              2 + v = persistent schedule, variant v */
     int reserved;
     double emin, emax;     /* spectral bounds used */
     double trace;          /* Tr D */

@@ -66,17 +66,13 @@ __device__ inline double wsum(double v) {
 
 // WN waves across the tile's columns (2: 4 waves of 64 x 64, 4: 8 waves of 64 x 32)
 template <int ST, int WN>
-__global__ __launch_bounds__(128 * WN) void k_square_f64(SquareArgs a) {
+__device__ __forceinline__ void f64_body(const SquareArgs& a, int t, unsigned char* __restrict__ lds,
+                                         double* __restrict__ red) {
     static_assert(ST >= 2 && ST <= 4, "stages");
     constexpr int kNW = 2 * WN;
     constexpr int kLPW = 2 * kBPR / kNW;   // direct loads per wave per stage
     constexpr int kNB = kBT / (16 * WN);   // 16 x 16 blocks per wave along columns
     constexpr int WTN = kBT / WN;
-    __shared__ __attribute__((aligned(16))) unsigned char lds[ST * kStage];
-    __shared__ double red[2 * kNW];
-
-    const int t = xcd_tile_index(blockIdx.x, a.per, a.ntiles);
-    if (t < 0) return;
     int I, J;
     tile_of(t, a.T, 8, &I, &J);
     const int np = a.np;
@@ -233,7 +229,35 @@ __global__ __launch_bounds__(128 * WN) void k_square_f64(SquareArgs a) {
     }
 }
 
+template <int ST, int WN>
+__global__ __launch_bounds__(128 * WN) void k_square_f64(SquareArgs a) {
+    __shared__ __attribute__((aligned(16))) unsigned char lds[ST * kStage];
+    __shared__ double red[4 * WN];
+    if (a.skip && *a.skip) return;
+    const int t = xcd_tile_index(blockIdx.x, a.per, a.ntiles);
+    if (t < 0) return;
+    f64_body<ST, WN>(a, t, lds, red);
+}
+
+// grouped: block b of problem p (offs[p] <= b < offs[p + 1]) computes tile b - offs[p]
+template <int ST, int WN>
+__global__ __launch_bounds__(128 * WN) void k_square_f64_g(const SquareArgs* __restrict__ descs,
+                                                          const int* __restrict__ offs, int nprob) {
+    __shared__ __attribute__((aligned(16))) unsigned char lds[ST * kStage];
+    __shared__ double red[4 * WN];
+    const int p = find_group(offs, nprob, blockIdx.x);
+    const SquareArgs a = descs[p];
+    if (a.skip && *a.skip) return;
+    f64_body<ST, WN>(a, blockIdx.x - offs[p], lds, red);
+}
+
 }  // namespace
+
+// grouped FP64 layer on 128 tiles (8 waves, 4 stages) over nprob problems
+hipError_t launch_square_f64_g(const SquareArgs* descs, const int* offs, int nprob, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_square_f64_g<4, 4>), dim3(blocks), dim3(512), 0, s, descs, offs, nprob);
+    return hipGetLastError();
+}
 
 // FP64 layer on 128 tiles (n_p a multiple of 128).  variant 0: 4 waves, 2 LDS stages;
 // 1: 4 waves, 4 stages (128 KB); 2: 8 waves, 4 stages.

@@ -160,9 +160,16 @@ struct Cfg {
     static_assert(LPW * (ST - 1) <= 48, "vmcnt range of wait_vm");
 };
 
-template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST, int PF>
-__global__ __launch_bounds__(64 * WM * WN) void k_square_sk(SquareArgs a, StreamK sk) {
+// The work of one workgroup.  ONE_TILE: exactly tile t0 over all of K (one workgroup per
+// tile, used by the grouped launch that covers many problems); otherwise the persistent
+// schedule of workgroup v: whole rounds, then at most one split-K tail chunk.
+// (The LDS arrays are declared here, not passed in: a generic pointer to them cast back to
+// an LDS address made the compiler emit an illegal instruction.)
+template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST, int PF, bool ONE_TILE>
+__device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, int v, int t0) {
     typedef Cfg<T16, WM, WN, MB, NB, SK, ST, PF> C;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS_ALL];
+    __shared__ int s_flag;
     typedef typename H2<T16>::vec8 vec8;
     typedef typename H2<T16>::vec4 vec4;
     constexpr int BT = C::BT;
@@ -170,17 +177,11 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_sk(SquareArgs a, Stream
     constexpr int ROW = C::ROW;
     constexpr int UPS = C::UPS;
 
-    __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS_ALL];
-    __shared__ int s_flag;
-
-    if (a.skip && *a.skip) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WN, wn = wave % WN;
     const int np = a.np;
     const int KS = np / SK;    // K-slices per tile
-    // XCD-aware order: the workgroups of one XCD get consecutive virtual indices
     const int G = sk.grid;
-    const int v = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
 
     // lane L of a direct load fills LDS bytes [16 L, 16 L + 16) of 1 KB block q: panel
     // row q RPB + L / CPR, physical chunk L % CPR, i.e. logical chunk
@@ -196,10 +197,14 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_sk(SquareArgs a, Stream
     const float alpha = a.coef[0], beta = a.coef[1], gamma = a.coef[2];
 
     // work items: whole rounds, then at most one tail chunk
-    const int items = sk.rounds + ((sk.tail_tiles > 0 && v < sk.tail_tiles * sk.chunks) ? 1 : 0);
+    const int items = ONE_TILE ? 1 : sk.rounds + ((sk.tail_tiles > 0 && v < sk.tail_tiles * sk.chunks) ? 1 : 0);
     for (int item = 0; item < items; ++item) {
         int t, kb, ke, chunk = -1, tail_tile = 0;
-        if (item < sk.rounds) {
+        if (ONE_TILE) {
+            t = t0;
+            kb = 0;
+            ke = KS;
+        } else if (item < sk.rounds) {
             t = item * G + v;
             kb = 0;
             ke = KS;
@@ -558,7 +563,86 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_sk(SquareArgs a, Stream
     }
 }
 
+template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST, int PF>
+__global__ __launch_bounds__(64 * WM * WN) void k_square_sk(SquareArgs a, StreamK sk) {
+    if (a.skip && *a.skip) return;
+    // XCD-aware order: the workgroups of one XCD get consecutive virtual indices
+    const int v = (blockIdx.x & 7) * (sk.grid >> 3) + (blockIdx.x >> 3);
+    sk_body<T16, WM, WN, MB, NB, SK, ST, PF, false>(a, sk, v, 0);
+}
+
+// One workgroup per upper-triangle tile of one problem, XCD-aware tile order.
+template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST>
+__global__ __launch_bounds__(64 * WM * WN) void k_square_dp(SquareArgs a) {
+    if (a.skip && *a.skip) return;
+    const int t = xcd_tile_index(blockIdx.x, a.per, a.ntiles);
+    if (t < 0) return;
+    StreamK none;
+    none.grid = 0;
+    none.rounds = 0;
+    none.tail_tiles = 0;
+    none.chunks = 1;
+    none.partial = nullptr;
+    none.counter = nullptr;
+    sk_body<T16, WM, WN, MB, NB, SK, ST, 0, true>(a, none, 0, t);
+}
+
+// One workgroup per upper-triangle tile, for one problem (descs[0], offs = {0, ntiles})
+// or many: block b belongs to problem p with offs[p] <= b < offs[p + 1] and computes its
+// tile b - offs[p].
+template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST>
+__global__ __launch_bounds__(64 * WM * WN) void k_square_dp_g(const SquareArgs* __restrict__ descs,
+                                                             const int* __restrict__ offs, int nprob) {
+    const int p = find_group(offs, nprob, blockIdx.x);
+    const SquareArgs a = descs[p];
+    if (a.skip && *a.skip) return;
+    StreamK none;
+    none.grid = 0;
+    none.rounds = 0;
+    none.tail_tiles = 0;
+    none.chunks = 1;
+    none.partial = nullptr;
+    none.counter = nullptr;
+    sk_body<T16, WM, WN, MB, NB, SK, ST, 0, true>(a, none, 0, blockIdx.x - offs[p]);
+}
+
 }  // namespace
+
+// Per-tile (one workgroup per tile) forms of the same pipeline.  Variants per tile edge,
+// as (waves, K-slice halves, LDS stages): 256: (8, 32, 2), (4, 32, 2); 128: (4, 32, 2),
+// (4, 64, 2), (4, 16, 4).  descs == nullptr: the single problem `a` (XCD-aware order, grid
+// 8 a.per); otherwise the grouped launch over nprob problems (blocks = offs[nprob]).
+template <typename T16>
+hipError_t launch_dp_t(int tile, int variant, const SquareArgs& a, const SquareArgs* descs, const int* offs,
+                       int nprob, int blocks, hipStream_t s) {
+#define SP2_L(WM, WN, MB, NB, SK, ST)                                                                       \
+    do {                                                                                                   \
+        if (descs)                                                                                         \
+            hipLaunchKernelGGL((k_square_dp_g<T16, WM, WN, MB, NB, SK, ST>), dim3(blocks), dim3(64 * WM * WN), \
+                               0, s, descs, offs, nprob);                                                  \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_square_dp<T16, WM, WN, MB, NB, SK, ST>), dim3(8 * a.per), dim3(64 * WM * WN), \
+                               0, s, a);                                                                   \
+    } while (0)
+    if (tile == 256) {
+        switch (variant) {
+            case 0: SP2_L(2, 4, 4, 2, 32, 2); break;
+            case 1: SP2_L(2, 2, 4, 4, 32, 2); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else if (tile == 128) {
+        switch (variant) {
+            case 0: SP2_L(2, 2, 2, 2, 32, 2); break;
+            case 1: SP2_L(2, 2, 2, 2, 64, 2); break;
+            case 2: SP2_L(2, 2, 2, 2, 16, 4); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef SP2_L
+    return hipGetLastError();
+}
 
 template <typename T16>
 hipError_t launch_sk_t(int tile, int variant, const SquareArgs& a, const StreamK& sk, hipStream_t s) {

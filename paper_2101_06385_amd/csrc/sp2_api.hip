@@ -48,7 +48,7 @@ bool read_opts(const sp2_options* o, Opts* r) {
     if (r->max_layers < 1 || r->max_layers >= SP2_MAX_LAYERS) return false;
     if (r->tile != 0 && r->tile != 64 && r->tile != 128 && r->tile != 256) return false;
     if (r->tile == 256 && !split) return false;
-    if (r->kernel < 0 || r->kernel > 1 + kSkVariants) return false;
+    if (r->kernel < 0 || (r->kernel > 1 + kSkVariants && r->kernel != 8)) return false;
     if (r->precision == SP2_FP64 && r->kernel > 4) return false;
     if (!isfinite(r->eps)) return false;
     if (r->have_bounds && !(isfinite(r->emin) && isfinite(r->emax) && r->emax > r->emin)) return false;
@@ -70,7 +70,7 @@ struct Plan {
 // choice takes the persistent schedule for 256 tiles only: with 128 tiles two one-tile
 // workgroups per CU measured faster.
 bool sk_wanted(bool split, int tile, int kernel) {
-    if (!split || tile < 128 || kernel == 1) return false;
+    if (!split || tile < 128 || kernel == 1 || kernel == 8) return false;
     return kernel != 0 || tile == 256;
 }
 
@@ -95,6 +95,14 @@ bool sk_resolve(const Plan& p, StreamK* sk, int* variant) {
     return square_sk_plan(p.tile_main, *variant, p.np, cus, &per_cu, sk, &T, &nt);
 }
 
+// Split layer with one workgroup per tile: the direct-to-LDS pipeline for 128/256 tiles
+// (kernel option 0/1), the register-staged kernel for 64 tiles or kernel option 8.
+constexpr int kKernelLegacyTile = 8;
+hipError_t launch_split_tile_layer(int precision, int tile, int kernel, const SquareArgs& a, hipStream_t s) {
+    if ((tile == 128 || tile == 256) && kernel != kKernelLegacyTile) return launch_square_dp(precision, tile, 0, a, s);
+    return launch_square_split(precision, tile, a, s);
+}
+
 // FP64 layer: the direct-load kernel on 128 tiles (kernel 2 / 3 / 4 = its variants 0 / 1 /
 // 2, 0 = automatic), the register-staged plain kernel for 64 tiles or kernel 1.
 constexpr int kF64AutoVariant = 2;
@@ -104,9 +112,10 @@ hipError_t launch_f64_layer(int tile, int kernel, const SquareArgs& a, hipStream
 }
 
 int auto_tile_main(int n, bool split) {
-    // split modes: 256 tiles once there are enough of them for every CU (stream-K needs
-    // at least one tile per workgroup), 128 below that
-    if (split) return n <= 256 ? 64 : (n < 6144 ? 128 : 256);
+    // split modes: 256 tiles from n = 4096 (136 tiles; measured 690 vs 624 TFLOP/s for
+    // 128 tiles there), persistent once there is a 256 tile per CU (n >= 6144); 128 tiles
+    // below 4096, 64 up to 256
+    if (split) return n <= 256 ? 64 : (n < 4096 ? 128 : 256);
     return n <= 512 ? 64 : 128;
 }
 
@@ -192,7 +201,7 @@ void fill_info(const DevState& st, const Plan* p, sp2_info* info) {
     if (p) {
         StreamK sk;
         int variant = 0;
-        info->kernel = sk_resolve(*p, &sk, &variant) ? 2 + variant : 1;
+        info->kernel = sk_resolve(*p, &sk, &variant) ? 2 + variant : (p->kernel == 8 ? 8 : 1);
     }
 }
 
@@ -458,7 +467,7 @@ static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, in
             if (use_sk)
                 SP2_TRY(launch_square_sk(o.precision, p.tile_main, sk_variant, a, sk, s));
             else if (p.split)
-                SP2_TRY(launch_square_split(o.precision, p.tile_main, a, s));
+                SP2_TRY(launch_split_tile_layer(o.precision, p.tile_main, p.kernel, a, s));
             else if (o.precision == SP2_FP64)
                 SP2_TRY(launch_f64_layer(p.tile_main, o.kernel, a, s));
             else
@@ -576,7 +585,7 @@ int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int ker
     if (precision < SP2_FP64 || precision > SP2_BF16X2) return SP2_EINVAL;
     const bool split = precision == SP2_FP16X2 || precision == SP2_BF16X2;
     if (tile != 0 && tile != 64 && tile != 128 && !(tile == 256 && split)) return SP2_EINVAL;
-    if (kernel < 0 || kernel > 1 + kSkVariants) return SP2_EINVAL;
+    if (kernel < 0 || (kernel > 1 + kSkVariants && kernel != 8)) return SP2_EINVAL;
     if (precision == SP2_FP64 && kernel > 4) return SP2_EINVAL;
     if (scale_log2 < 0) scale_log2 = precision == SP2_FP16X2 ? 12 : 0;
     if (!split) scale_log2 = 0;
@@ -634,7 +643,7 @@ int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int ker
             SP2_TRY(launch_zero_ints(sk.counter, kMaxSkGrid, s));
             SP2_TRY(launch_square_sk(precision, t, variant, a, sk, s));
         } else {
-            SP2_TRY(launch_square_split(precision, t, a, s));
+            SP2_TRY(launch_split_tile_layer(precision, t, kernel, a, s));
         }
     } else if (precision == SP2_FP64) {
         a.x0 = dX;
@@ -670,13 +679,13 @@ struct BatchLayout {
 
 bool batch_layout(int batch, const int* n, const int* n_occ, const Opts& o, BatchLayout* L) {
     L->batch = batch;
-    int nmin = 1 << 30;
-    for (int i = 0; i < batch; ++i) nmin = n[i] < nmin ? n[i] : nmin;
+    int nmax = 0;
+    for (int i = 0; i < batch; ++i) nmax = n[i] > nmax ? n[i] : nmax;
     int tuned = 0, tuned_kernel = 0;
     if (o.tile == 0 && tune_lookup(kTuneBatched, o.precision, tune_key_batched(batch, n), &tuned, &tuned_kernel))
         L->tile = tuned;
     else
-        L->tile = o.tile ? o.tile : (nmin <= 256 ? 64 : 128);
+        L->tile = o.tile ? o.tile : (nmax < 1024 ? 64 : 128);
     if (L->tile == 256) L->tile = 128;
     L->plans.resize(batch);
     L->region.resize(batch);
@@ -868,11 +877,13 @@ int sp2_density_batched(int batch, const double* const* dH, const int* ldh, doub
                 if (o.precision == SP2_FP32)
                     SP2_TRY(launch_square_plain_g(SP2_FP32, L.tile, a, d_om, nt, o_m[nt], s));
                 else
-                    SP2_TRY(launch_square_split_g(o.precision, L.tile, a, d_om, nt, o_m[nt], s));
+                    SP2_TRY(L.tile == 128 ? launch_square_dp_g(o.precision, 128, 0, a, d_om, nt, o_m[nt], s)
+                                          : launch_square_split_g(o.precision, L.tile, a, d_om, nt, o_m[nt], s));
             }
             SP2_TRY(launch_batch_select(d_probs, nt, 64, s));
-            SP2_TRY(launch_square_plain_g(SP2_FP64, L.tile, d_sq + 2 * nt, d_or, nt, o_r[nt], s));
-            SP2_TRY(launch_square_plain_g(SP2_FP64, L.tile, d_sq + 3 * nt, d_or, nt, o_r[nt], s));
+            for (int step = 2; step <= 3; ++step)
+                SP2_TRY(L.tile == 128 ? launch_square_f64_g(d_sq + step * nt, d_or, nt, o_r[nt], s)
+                                      : launch_square_plain_g(SP2_FP64, L.tile, d_sq + step * nt, d_or, nt, o_r[nt], s));
             SP2_TRY(launch_batch_dstats(d_probs, d_od, nt, o_d[nt], s));
             SP2_TRY(launch_batch_finalize(d_probs, nt, s));
             return SP2_OK;

@@ -186,6 +186,7 @@ hipError_t launch_square_split(int precision, int tile, const SquareArgs& a, hip
 hipError_t launch_square_plain(int precision, int tile, const SquareArgs& a, hipStream_t s);
 // FP64 layer with direct-to-LDS staging, 128 tiles (k_square_f64.hip); variant 0 or 1
 hipError_t launch_square_f64(int variant, const SquareArgs& a, hipStream_t s);
+hipError_t launch_square_f64_g(const SquareArgs* descs, const int* offs, int nprob, int blocks, hipStream_t s);
 hipError_t launch_square_split_g(int precision, int tile, const SquareArgs* descs, const int* offs, int nprob,
                                  int blocks, hipStream_t s);
 hipError_t launch_square_plain_g(int precision, int tile, const SquareArgs* descs, const int* offs, int nprob,
@@ -197,6 +198,10 @@ bool square_sk_plan(int tile, int variant, int np, int cus, int* wg_per_cu, Stre
 size_t square_sk_partial_bytes(int tile, int np);
 hipError_t launch_square_sk(int precision, int tile, int variant, const SquareArgs& a, const StreamK& sk,
                             hipStream_t s);
+// the same pipeline with one workgroup per tile (tiles 128, 256): one problem, or grouped
+hipError_t launch_square_dp(int precision, int tile, int variant, const SquareArgs& a, hipStream_t s);
+hipError_t launch_square_dp_g(int precision, int tile, int variant, const SquareArgs* descs, const int* offs,
+                              int nprob, int blocks, hipStream_t s);
 hipError_t launch_zero_ints(int* p, int count, hipStream_t s);
 
 // preparation / control kernels (k_prep.hip)

@@ -84,7 +84,8 @@ def test_invalid_options_give_zero_workspace():
     assert sp2.workspace_size(100, sp2.options(precision="fp64", tile=256)) == 0
     assert sp2.workspace_size(100, sp2.options(bounds=(1.0, -1.0))) == 0
     assert sp2.workspace_size(100, sp2.options(precision="fp16x2", scale_log2=15)) == 0
-    assert sp2.workspace_size(100, sp2.options(kernel=8)) == 0
+    assert sp2.workspace_size(100, sp2.options(kernel=9)) == 0
+    assert sp2.workspace_size(100, sp2.options(kernel=8)) > 0
     assert sp2.workspace_size(100, sp2.options(kernel=-1)) == 0
     assert sp2.workspace_size(100, sp2.options(kernel=7, tile=128)) > 0
     assert sp2.workspace_size(100, sp2.options(precision="fp64", kernel=5)) == 0

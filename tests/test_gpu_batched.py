@@ -35,6 +35,21 @@ def test_batched_matches_single_path_bitwise(prec):
             _check_vs_oracle(w, d, info)
 
 
+@pytest.mark.parametrize("prec", ["fp16x2", "bf16x2"])
+def test_batched_tile128_matches_single_path_bitwise(prec):
+    """Grouped 128-tile launches (direct-to-LDS squaring, FP64 refinement kernel) against
+    the single path with the same tile and one workgroup per tile."""
+    ws = [wl.gapped(50 + i, n, n // 4) for i, n in enumerate((520, 700, 900))]
+    hs = [torch.from_numpy(w.h).to(DEV) for w in ws]
+    outs, infos = sp2.density_batched(hs, [w.n_occ for w in ws], precision=prec, tile=128)
+    for w, h, d, info in zip(ws, hs, outs, infos):
+        d1, i1 = sp2.density(h, w.n_occ, precision=prec, tile=128, kernel=1)
+        assert info["layers"] == i1["layers"] and info["sigma"] == i1["sigma"]
+        assert torch.equal(d, d1), w.name
+        if prec == "fp16x2":
+            _check_vs_oracle(w, d, info)
+
+
 def test_batched_graph_and_stream_launch_agree():
     ws = [wl.gapped(60 + i, n, int(0.4 * n)) for i, n in enumerate((100, 300, 520))]
     hs = [torch.from_numpy(w.h).to(DEV) for w in ws]

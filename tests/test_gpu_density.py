@@ -211,3 +211,18 @@ def test_async_call_and_query():
     assert info is None
     q = sp2.query(ws, 300, "fp16x2")
     assert q["status"] == sp2.SP2_OK and q["layers"] > 10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x2"])
+def test_layers_after_the_stop_do_no_work(prec):
+    """Synchronous calls enqueue up to two chunks of layers beyond the stopping layer; those
+    must return at once (skip flag) and leave S_{m-1} for the refinement untouched."""
+    w = wl.gapped(77, 1100, 300)
+    h = torch.from_numpy(w.h).to(DEV)
+    _, info, tm = sp2.density(h, w.n_occ, precision=prec, timed=True)
+    m = info["layers"]
+    ran = tm["square_ms"][:m - 1]
+    extra = [t for t in tm["square_ms"][m - 1:] if t > 0]
+    assert extra, "expected layers enqueued after the stop"
+    assert max(extra) < 0.2 * float(np.median(ran)), (max(extra), float(np.median(ran)))
+    assert info["status"] == 0

@@ -34,7 +34,7 @@ def _check_sums(y, sums):
 
 @pytest.mark.parametrize("prec,tile,n", [
     ("fp16x2", 64, 200), ("fp16x2", 128, 300), ("fp16x2", 256, 520), ("fp16x2", 256, 1024),
-    ("bf16x2", 64, 130), ("bf16x2", 128, 300), ("bf16x2", 256, 600),
+    ("bf16x2", 64, 130), ("bf16x2", 128, 300), ("bf16x2", 256, 600), ("fp16x2", 128, 1000),
 ])
 def test_split_square_vs_exact_products(prec, tile, n):
     fmt = "fp16" if prec == "fp16x2" else "bf16"
@@ -83,6 +83,7 @@ def test_plain_square_vs_fp64(prec, tile, n):
     ("fp16x2", 128, 2, 4100), ("fp16x2", 128, 3, 4100), ("fp16x2", 128, 4, 4100), ("fp16x2", 128, 5, 4100),
     ("fp16x2", 256, 6, 6100), ("fp16x2", 256, 7, 6100), ("fp16x2", 128, 6, 4100), ("fp16x2", 128, 7, 4100),
     ("bf16x2", 256, 3, 6100), ("bf16x2", 128, 3, 4100), ("bf16x2", 256, 7, 6100), ("fp16x2", 256, 1, 6100),
+    ("fp16x2", 128, 1, 4100), ("bf16x2", 128, 1, 4100), ("fp16x2", 256, 8, 6100), ("fp16x2", 128, 8, 4100),
 ])
 def test_persistent_schedules_sampled_rows(prec, tile, kernel, n):
     """Persistent schedules, every kernel variant (only used once there are at least as
