@@ -6,7 +6,7 @@
 // This file holds what the network adds:
 //   k_pack_coef   : (W, B, c) device arrays -> per-layer coefficient triples
 //   k_copy_pad    : n x n (leading dimension ld) <-> zero-padded n_p x n_p
-//   k_adjoint     : one reverse layer.  With G = dL/dX_{k+1} (symmetric),
+//   k_adjoint_dl  : one reverse layer.  With G = dL/dX_{k+1} (symmetric),
 //                   M = G X_k + X_k G,  G_k = W_k M + B_k G,
 //                   and the FP64 tile partials of  Tr G (= dL/dc_k),
 //                   <G, X_k>_F (= dL/dB_k)  and  <M, X_k>_F / 2 = <G, X_k^2>_F (= dL/dW_k).
@@ -20,7 +20,6 @@ namespace sp2 {
 namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 
@@ -54,107 +53,152 @@ __device__ inline double wsum(double v) {
     return v;
 }
 
-// FP32 adjoint layer.  Output tiles (I <= J) of the symmetric M = G X + X G: panel I of G
-// against panel J of X plus panel I of X against panel J of G (rows of a symmetric matrix
-// are its columns, so all four operands are K-contiguous row panels).
-template <int BT, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN) void k_adjoint(AdjointArgs a) {
-    constexpr int NT = 64 * WM * WN;
-    constexpr int WTM = BT / WM, WTN = BT / WN;
-    constexpr int MB = WTM / 32, NB = WTN / 32;
-    constexpr int BK = 32;                 // floats per row per stage
-    constexpr int LROW = BK + 1;           // padded row (floats)
-    constexpr int ARR = BT * LROW;
-    constexpr int CPR = BK / 4;            // 16-byte chunks per row
-    constexpr int CPT = BT * CPR / NT;     // chunks per thread per array
-    static_assert(CPT >= 1 && (BT * CPR) % NT == 0, "tile / thread mismatch");
+// FP32 adjoint layer on output tiles (I <= J) of the symmetric M = G X + X G (rows of a
+// symmetric matrix are its columns, so all four operands are K-contiguous row panels).
+// The four row panels (G_I, X_I,
+// X_J, G_J) go from global memory into LDS with global_load_lds_dwordx4 in K-stages of 32
+// floats (one 128-byte line per row; 1 KB blocks of 8 rows, 16-byte chunks XOR-swizzled by
+// (row >> 1) & 7), two stages deep, issued from inline asm with explicit vmcnt accounting
+// and spread among the MFMAs.  Each lane permutes its K order inside a unit of 8: MFMA s
+// (0..3) takes, in its K lane j = lane / 32, the index 8 h + 4 j + s, for A and B alike, so
+// one 16-byte LDS read feeds four v_mfma_f32_32x32x2f32.  4 waves of BT/2 x BT/2.
+namespace dl {
+constexpr int kBK = 32, kRow = 128, kRPB = 8, kST = 2;
 
-    __shared__ float lds[2 * 4 * ARR];
-    __shared__ double red[3 * (NT / 64)];
+__device__ inline int swz8(int r) { return (r >> 1) & 7; }
+typedef __attribute__((address_space(3))) unsigned char lds_byte;
+__device__ __forceinline__ unsigned lds_addr(const unsigned char* p) {
+    return (unsigned)(uintptr_t)(const lds_byte*)p;
+}
+__device__ __forceinline__ void dma16(const void* g, unsigned lds_base) {
+    asm volatile(
+        "s_mov_b32 m0, %1\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dwordx4 %0, off"
+        :
+        : "v"(g), "s"(lds_base)
+        : "memory", "m0");
+}
+__device__ __forceinline__ void wait_vm(int n) {
+    if (n >= 16) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+    else if (n >= 8) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+}  // namespace dl
 
+// BT = 128 (2 x 2 blocks of 32 x 32 per wave) or 64 (one block per wave)
+template <int BT>
+__global__ __launch_bounds__(256) void k_adjoint_dl(AdjointArgs a) {
+    using namespace dl;
+    constexpr int kBT = BT, kArr = kBT * kRow, kStage = 4 * kArr;
+    constexpr int kBPR = kBT / kRPB, kLPW = 4 * kBPR / 4;   // direct loads per wave per stage
+    constexpr int NB = BT / 64;                             // 32 x 32 blocks per wave and dimension
+    constexpr int WT = BT / 2;                              // wave tile edge
+    constexpr int NM = 4 * NB * NB * 2;                     // MFMAs per unit
+    static_assert(NM % kLPW == 0, "loads spread evenly over the MFMAs");
+    __shared__ __attribute__((aligned(16))) unsigned char lds[kST * kStage];
+    __shared__ double red[3 * 4];
     const int t = xcd_tile_index(blockIdx.x, a.per, a.ntiles);
     if (t < 0) return;
     int I, J;
     tile_of(t, a.T, 8, &I, &J);
     const int np = a.np;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave / WN, wn = wave % WN;
+    const int wm = wave >> 1, wn = wave & 1;
     // stage arrays: 0 = G panel I, 1 = X panel I, 2 = X panel J, 3 = G panel J
-    const float* src[4] = {a.g + (size_t)I * BT * np, a.x + (size_t)I * BT * np, a.x + (size_t)J * BT * np,
-                           a.g + (size_t)J * BT * np};
+    const float* src[4] = {a.g + (size_t)I * kBT * np, a.x + (size_t)I * kBT * np, a.x + (size_t)J * kBT * np,
+                           a.g + (size_t)J * kBT * np};
+    const int nsl = np / kBK;
 
-    f32x16 acc[MB][NB];
-#pragma unroll
-    for (int m = 0; m < MB; ++m)
-#pragma unroll
-        for (int n = 0; n < NB; ++n)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[m][n][r] = 0.f;
-
-    f32x4 stg[4][CPT];
-    auto gload = [&](int k0) {
-#pragma unroll
-        for (int arr = 0; arr < 4; ++arr)
-#pragma unroll
-            for (int i = 0; i < CPT; ++i) {
-                const int q = tid + i * NT;
-                const int r = q / CPR, c = q % CPR;
-                stg[arr][i] = *(const f32x4*)(src[arr] + (size_t)r * np + k0 + c * 4);
-            }
+    auto load_one = [&](int buf, int ks, int l) {
+        const int j = wave * kLPW + l;
+        const int arr = j / kBPR, qd = j % kBPR;
+        const int row = qd * kRPB + (lane >> 3);
+        const float* g = src[arr] + (size_t)row * np + ks * kBK + (((lane & 7) ^ swz8(row)) << 2);
+        dma16(g, __builtin_amdgcn_readfirstlane(lds_addr(lds + buf * kStage + arr * kArr + qd * 1024)));
     };
-    auto lstore = [&](int buf) {
+    typedef float f32x4v __attribute__((ext_vector_type(4)));
+    // fragments of unit h (K 8h .. 8h+7) in buffer buf: lane reads the 16-byte logical chunk
+    // 2h + lane / 32 of row (block base + lane % 32) of each panel
+    auto frags = [&](int buf, int h, f32x4v (&fg)[NB], f32x4v (&fx)[NB], f32x4v (&hx)[NB], f32x4v (&hg)[NB]) {
+        const unsigned char* base = lds + buf * kStage;
+        const int r32 = lane & 31;
 #pragma unroll
-        for (int arr = 0; arr < 4; ++arr)
-#pragma unroll
-            for (int i = 0; i < CPT; ++i) {
-                const int q = tid + i * NT;
-                const int r = q / CPR, c = q % CPR;
-                float* dst = lds + (buf * 4 + arr) * ARR + r * LROW + c * 4;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) dst[e] = stg[arr][i][e];
-            }
-    };
-
-    const int KT = np / BK;
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    for (int kt = 0; kt < KT; ++kt) {
-        const int buf = kt & 1;
-        gload((kt + 1 < KT ? kt + 1 : kt) * BK);
-        const float* gI = lds + (buf * 4 + 0) * ARR;
-        const float* xI = lds + (buf * 4 + 1) * ARR;
-        const float* xJ = lds + (buf * 4 + 2) * ARR;
-        const float* gJ = lds + (buf * 4 + 3) * ARR;
-#pragma unroll
-        for (int ks = 0; ks < BK / 2; ++ks) {
-            const int k = 2 * ks + (lane >> 5);
-            float ga[MB], xa[MB], xb[NB], gb[NB];
-#pragma unroll
-            for (int m = 0; m < MB; ++m) {
-                const int r = (wm * WTM + m * 32 + (lane & 31)) * LROW + k;
-                ga[m] = gI[r];
-                xa[m] = xI[r];
-            }
-#pragma unroll
-            for (int n = 0; n < NB; ++n) {
-                const int r = (wn * WTN + n * 32 + (lane & 31)) * LROW + k;
-                xb[n] = xJ[r];
-                gb[n] = gJ[r];
-            }
-#pragma unroll
-            for (int m = 0; m < MB; ++m)
-#pragma unroll
-                for (int n = 0; n < NB; ++n)
-                    acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x2f32(ga[m], xb[n], acc[m][n], 0, 0, 0);
-#pragma unroll
-            for (int m = 0; m < MB; ++m)
-#pragma unroll
-                for (int n = 0; n < NB; ++n)
-                    acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x2f32(xa[m], gb[n], acc[m][n], 0, 0, 0);
+        for (int m = 0; m < NB; ++m) {
+            const int row = wm * WT + m * 32 + r32;
+            const int off = row * kRow + ((((h << 1) + (lane >> 5)) ^ swz8(row)) << 4);
+            fg[m] = *(const f32x4v*)(base + off);
+            fx[m] = *(const f32x4v*)(base + kArr + off);
         }
-        lstore(buf ^ 1);
-        __syncthreads();
+#pragma unroll
+        for (int n = 0; n < NB; ++n) {
+            const int row = wn * WT + n * 32 + r32;
+            const int off = row * kRow + ((((h << 1) + (lane >> 5)) ^ swz8(row)) << 4);
+            hx[n] = *(const f32x4v*)(base + 2 * kArr + off);
+            hg[n] = *(const f32x4v*)(base + 3 * kArr + off);
+        }
+    };
+    // one accumulator per product (G_I X_J^T and X_I G_J^T): two independent MFMA chains
+    f32x16 acc[2][NB][NB];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int m = 0; m < NB; ++m)
+#pragma unroll
+            for (int n = 0; n < NB; ++n)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[q][m][n][r] = 0.f;
+    // the NM MFMAs of one unit (G_I X_J^T + X_I G_J^T), with the kLPW direct loads of stage
+    // ks into buffer buf spread evenly among them when doit
+    auto mma = [&](const f32x4v (&fg)[NB], const f32x4v (&fx)[NB], const f32x4v (&hx)[NB], const f32x4v (&hg)[NB],
+                   int buf, int ks, bool doit) {
+        constexpr int EVERY = NM / kLPW;
+#pragma unroll
+        for (int i = 0; i < NM; ++i) {
+            const int s = i / (2 * NB * NB), pr = (i / (NB * NB)) & 1, m = (i / NB) % NB, n = i % NB;
+            if (pr == 0)
+                acc[0][m][n] = __builtin_amdgcn_mfma_f32_32x32x2f32(fg[m][s], hx[n][s], acc[0][m][n], 0, 0, 0);
+            else
+                acc[1][m][n] = __builtin_amdgcn_mfma_f32_32x32x2f32(fx[m][s], hg[n][s], acc[1][m][n], 0, 0, 0);
+            if (i % EVERY == EVERY - 1) {
+                __builtin_amdgcn_sched_barrier(0);
+                if (doit) load_one(buf, ks, i / EVERY);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    };
+
+    const int pro = nsl < kST ? nsl : kST;
+    for (int q = 0; q < pro; ++q)
+        for (int l = 0; l < kLPW; ++l) load_one(q, q, l);
+    wait_vm((pro - 1) * kLPW);
+    __syncthreads();
+    f32x4v pg[NB], px[NB], phx[NB], phg[NB], qg[NB], qx[NB], qhx[NB], qhg[NB];
+    frags(0, 0, pg, px, phx, phg);
+    // Stages of 4 units, the units alternating between fragment sets P and Q.  After the
+    // third unit of stage st: wait for stage st + 1 (the only loads in flight) and the
+    // barrier (every wave has read stage st), then stage st + 2 refills stage st's buffer
+    // among the MFMAs of its fourth unit.
+    for (int st = 0; st < nsl; ++st) {
+        const int buf = st % kST;
+        // units 0, 1
+        frags(buf, 1, qg, qx, qhx, qhg);
+        mma(pg, px, phx, phg, 0, 0, false);
+        frags(buf, 2, pg, px, phx, phg);
+        mma(qg, qx, qhx, qhg, 0, 0, false);
+        // units 2, 3
+        frags(buf, 3, qg, qx, qhx, qhg);
+        mma(pg, px, phx, phg, 0, 0, false);
+        if (st + 1 < nsl) {
+            // stage st + 1 readable; the buffer of stage st is free once every wave has read
+            // unit 3 above (the barrier), and is refilled with stage st + 2
+            wait_vm(0);
+            __syncthreads();
+            frags((st + 1) % kST, 0, pg, px, phx, phg);
+            mma(qg, qx, qhx, qhg, buf, st + 2, st + 2 < nsl);
+        } else {
+            mma(qg, qx, qhx, qhg, 0, 0, false);
+        }
     }
 
     // epilogue: G_k = W M + B G over row <= col, mirrored; FP64 partials
@@ -162,16 +206,16 @@ __global__ __launch_bounds__(64 * WM * WN) void k_adjoint(AdjointArgs a) {
     const bool diag = (I == J);
     double p_tr = 0.0, p_gx = 0.0, p_mx = 0.0;
 #pragma unroll
-    for (int m = 0; m < MB; ++m) {
+    for (int m = 0; m < NB; ++m) {
 #pragma unroll
         for (int n = 0; n < NB; ++n) {
-            const int col = J * BT + wn * WTN + n * 32 + (lane & 31);
+            const int col = J * kBT + wn * WT + n * 32 + (lane & 31);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int row = I * BT + wm * WTM + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int row = I * kBT + wm * WT + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                 if (diag && row > col) continue;
                 const size_t off = (size_t)row * np + col;
-                const float mv = acc[m][n][r];
+                const float mv = acc[0][m][n][r] + acc[1][m][n][r];
                 const float gv = a.g[off];
                 const float xv = a.x[off];
                 const float gn = fmaf(wk, mv, bk * gv);
@@ -195,7 +239,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_adjoint(AdjointArgs a) {
     __syncthreads();
     if (tid == 0) {
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (int w = 0; w < NT / 64; ++w) {
+        for (int w = 0; w < 4; ++w) {
             s0 += red[3 * w];
             s1 += red[3 * w + 1];
             s2 += red[3 * w + 2];
@@ -266,9 +310,9 @@ int adjoint_grid(int tile, int np, int* T, int* ntiles, int* per) {
 hipError_t launch_adjoint(int tile, const AdjointArgs& a, hipStream_t s) {
     const int grid = 8 * a.per;
     if (tile == 128)
-        hipLaunchKernelGGL((k_adjoint<128, 2, 2>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_adjoint_dl<128>), dim3(grid), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL((k_adjoint<64, 2, 2>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_adjoint_dl<64>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -33,7 +33,9 @@ bool net_plan(int n, int K, int precision, int ckpt_every, NetPlan* p) {
     if (p->c > K) p->c = K;
     p->nck = (K + p->c - 1) / p->c;
     p->tile_main = n <= 256 ? 64 : 128;
-    p->tile_adj = n <= 512 ? 64 : 128;
+    // adjoint tile: 64 until 128 tiles fill the GPU (136 tiles of 128 at n = 2048 left
+    // half the CUs idle)
+    p->tile_adj = n <= 4096 ? 64 : 128;
     const int m = p->tile_main > p->tile_adj ? p->tile_main : p->tile_adj;
     p->np = round_up(n, m);
     if (p->split)
@@ -123,6 +125,7 @@ hipError_t layer(const NetPlan& p, const NetBuffers& b, int k, const float* x_in
     a.per = p.per_main;
     a.out_scale = ldexpf(1.f, -2 * p.scale_log2);
     a.in_scale = ldexpf(1.f, p.scale_log2);
+    if (p.split && p.tile_main == 128) return launch_square_dp(p.precision, 128, 0, a, s);
     return p.split ? launch_square_split(p.precision, p.tile_main, a, s)
                    : launch_square_plain(p.precision, p.tile_main, a, s);
 }

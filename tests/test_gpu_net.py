@@ -73,6 +73,26 @@ def test_adjoint_matches_oracle_gradient(prec):
     assert np.abs(g0n - rg).max() <= tol * np.abs(rg).max()
 
 
+@pytest.mark.parametrize("prec,n,k", [("fp32", 700, 5), ("fp16x2", 900, 6)])
+def test_adjoint_128_tiles_matches_oracle_gradient(prec, n, k):
+    """Sizes above 512 run the 128-tile adjoint and forward kernels (several tiles and a
+    ragged edge): gradients and dL/dX_0 against the FP64 matrix adjoint."""
+    w, x0, wt, bt, ct, target = _problem(n, k, 7)
+    xt, wtt, btt, ctt = _t(x0), _t(wt), _t(bt), _t(ct)
+    xk, ws = sp2.net_forward(xt, wtt, btt, ctt, precision=prec)
+    gk = 2.0 * (xk.double() - _t(target)).float()
+    dw, db, dc, g0 = sp2.net_backward(gk, wtt, btt, ctt, ws, precision=prec)
+    loss, rw, rb, rc, rg = onet.loss_grad_matrix(x0.astype(np.float64), target, wt.astype(np.float64),
+                                                 bt.astype(np.float64), ct.astype(np.float64))
+    tol = 2e-4 if prec == "fp32" else 2e-3
+    for got, ref in ((dw, rw), (db, rb), (dc, rc)):
+        got = got.cpu().numpy().astype(np.float64)
+        assert np.abs(got - ref).max() <= tol * np.abs(ref).max(), (prec, got, ref)
+    g0n = g0.cpu().numpy().astype(np.float64)
+    assert np.abs(g0n - rg).max() <= tol * np.abs(rg).max()
+    assert np.array_equal(g0n, g0n.T)
+
+
 def test_adjoint_matches_central_differences_of_the_gpu_forward():
     """FP32 layers, h = 1e-2: the GPU backward equals the slope of the GPU forward."""
     n, k = 128, 5
