@@ -63,7 +63,7 @@ __device__ inline double wsum(double v) {
 // (0..3) takes, in its K lane j = lane / 32, the index 8 h + 4 j + s, for A and B alike, so
 // one 16-byte LDS read feeds four v_mfma_f32_32x32x2f32.  4 waves of BT/2 x BT/2.
 namespace dl {
-constexpr int kBK = 32, kRow = 128, kRPB = 8, kST = 2;
+constexpr int kBK = 32, kRow = 128, kRPB = 8;
 
 __device__ inline int swz8(int r) { return (r >> 1) & 7; }
 typedef __attribute__((address_space(3))) unsigned char lds_byte;
@@ -79,16 +79,24 @@ __device__ __forceinline__ void dma16(const void* g, unsigned lds_base) {
         : "v"(g), "s"(lds_base)
         : "memory", "m0");
 }
+// rounds n down to an available immediate (waiting for more is always safe)
 __device__ __forceinline__ void wait_vm(int n) {
-    if (n >= 16) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+    if (n >= 48) asm volatile("s_waitcnt vmcnt(48)" ::: "memory");
+    else if (n >= 32) asm volatile("s_waitcnt vmcnt(32)" ::: "memory");
+    else if (n >= 24) asm volatile("s_waitcnt vmcnt(24)" ::: "memory");
+    else if (n >= 16) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
     else if (n >= 8) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
     else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 }  // namespace dl
 
-// BT = 128 (2 x 2 blocks of 32 x 32 per wave) or 64 (one block per wave)
-template <int BT>
-__global__ __launch_bounds__(256) void k_adjoint_dl(AdjointArgs a) {
+// BT = 128 (2 x 2 blocks of 32 x 32 per wave) or 64 (one block per wave).  Persistent
+// schedule (as for the split squaring): sk.grid workgroups run whole rounds of tiles, then
+// the leftover tiles are cut along K into sk.chunks chunks each; every chunk stores its FP32
+// partial of M and the last of a tile's arrivals sums them in chunk order (deterministic)
+// and runs the epilogue.
+template <int BT, int kST>
+__global__ __launch_bounds__(256) void k_adjoint_dl(AdjointArgs a, StreamK sk) {
     using namespace dl;
     constexpr int kBT = BT, kArr = kBT * kRow, kStage = 4 * kArr;
     constexpr int kBPR = kBT / kRPB, kLPW = 4 * kBPR / 4;   // direct loads per wave per stage
@@ -96,157 +104,225 @@ __global__ __launch_bounds__(256) void k_adjoint_dl(AdjointArgs a) {
     constexpr int WT = BT / 2;                              // wave tile edge
     constexpr int NM = 4 * NB * NB * 2;                     // MFMAs per unit
     static_assert(NM % kLPW == 0, "loads spread evenly over the MFMAs");
+    typedef float f32x4v __attribute__((ext_vector_type(4)));
     __shared__ __attribute__((aligned(16))) unsigned char lds[kST * kStage];
     __shared__ double red[3 * 4];
-    const int t = xcd_tile_index(blockIdx.x, a.per, a.ntiles);
-    if (t < 0) return;
-    int I, J;
-    tile_of(t, a.T, 8, &I, &J);
+    __shared__ int s_flag;
+
     const int np = a.np;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    // stage arrays: 0 = G panel I, 1 = X panel I, 2 = X panel J, 3 = G panel J
-    const float* src[4] = {a.g + (size_t)I * kBT * np, a.x + (size_t)I * kBT * np, a.x + (size_t)J * kBT * np,
-                           a.g + (size_t)J * kBT * np};
-    const int nsl = np / kBK;
+    const int G = sk.grid;
+    const int v = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);   // XCD-aware order
+    const int nsl_all = np / kBK;
+    const int items = sk.rounds + ((sk.tail_tiles > 0 && v < sk.tail_tiles * sk.chunks) ? 1 : 0);
+    for (int item = 0; item < items; ++item) {
+        int t, kb, ke, chunk = -1, tail_tile = 0;
+        if (item < sk.rounds) {
+            t = item * G + v;
+            kb = 0;
+            ke = nsl_all;
+        } else {
+            tail_tile = v / sk.chunks;
+            chunk = v % sk.chunks;
+            t = sk.rounds * G + tail_tile;
+            kb = (int)(((long long)chunk * nsl_all) / sk.chunks);
+            ke = (int)(((long long)(chunk + 1) * nsl_all) / sk.chunks);
+        }
+        const int nsl = ke - kb;
+        int I, J;
+        tile_of(t, a.T, 8, &I, &J);
+        // stage arrays: 0 = G panel I, 1 = X panel I, 2 = X panel J, 3 = G panel J
+        const float* src[4] = {a.g + (size_t)I * kBT * np, a.x + (size_t)I * kBT * np,
+                               a.x + (size_t)J * kBT * np, a.g + (size_t)J * kBT * np};
 
-    auto load_one = [&](int buf, int ks, int l) {
-        const int j = wave * kLPW + l;
-        const int arr = j / kBPR, qd = j % kBPR;
-        const int row = qd * kRPB + (lane >> 3);
-        const float* g = src[arr] + (size_t)row * np + ks * kBK + (((lane & 7) ^ swz8(row)) << 2);
-        dma16(g, __builtin_amdgcn_readfirstlane(lds_addr(lds + buf * kStage + arr * kArr + qd * 1024)));
-    };
-    typedef float f32x4v __attribute__((ext_vector_type(4)));
-    // fragments of unit h (K 8h .. 8h+7) in buffer buf: lane reads the 16-byte logical chunk
-    // 2h + lane / 32 of row (block base + lane % 32) of each panel
-    auto frags = [&](int buf, int h, f32x4v (&fg)[NB], f32x4v (&fx)[NB], f32x4v (&hx)[NB], f32x4v (&hg)[NB]) {
-        const unsigned char* base = lds + buf * kStage;
-        const int r32 = lane & 31;
+        auto load_one = [&](int buf, int ks, int l) {
+            const int j = wave * kLPW + l;
+            const int arr = j / kBPR, qd = j % kBPR;
+            const int row = qd * kRPB + (lane >> 3);
+            const float* g = src[arr] + (size_t)row * np + ks * kBK + (((lane & 7) ^ swz8(row)) << 2);
+            dma16(g, __builtin_amdgcn_readfirstlane(lds_addr(lds + buf * kStage + arr * kArr + qd * 1024)));
+        };
+        // fragments of unit h (K 8h .. 8h+7) in buffer buf: lane reads the 16-byte logical
+        // chunk 2h + lane / 32 of row (block base + lane % 32) of each panel
+        auto frags = [&](int buf, int h, f32x4v (&fg)[NB], f32x4v (&fx)[NB], f32x4v (&hx)[NB], f32x4v (&hg)[NB]) {
+            const unsigned char* base = lds + buf * kStage;
+            const int r32 = lane & 31;
 #pragma unroll
-        for (int m = 0; m < NB; ++m) {
-            const int row = wm * WT + m * 32 + r32;
-            const int off = row * kRow + ((((h << 1) + (lane >> 5)) ^ swz8(row)) << 4);
-            fg[m] = *(const f32x4v*)(base + off);
-            fx[m] = *(const f32x4v*)(base + kArr + off);
+            for (int m = 0; m < NB; ++m) {
+                const int row = wm * WT + m * 32 + r32;
+                const int off = row * kRow + ((((h << 1) + (lane >> 5)) ^ swz8(row)) << 4);
+                fg[m] = *(const f32x4v*)(base + off);
+                fx[m] = *(const f32x4v*)(base + kArr + off);
+            }
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+                const int row = wn * WT + n * 32 + r32;
+                const int off = row * kRow + ((((h << 1) + (lane >> 5)) ^ swz8(row)) << 4);
+                hx[n] = *(const f32x4v*)(base + 2 * kArr + off);
+                hg[n] = *(const f32x4v*)(base + 3 * kArr + off);
+            }
+        };
+        // one accumulator per product (G_I X_J^T and X_I G_J^T): two independent MFMA chains
+        f32x16 acc[2][NB][NB];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int m = 0; m < NB; ++m)
+#pragma unroll
+                for (int n = 0; n < NB; ++n)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc[q][m][n][r] = 0.f;
+        // the NM MFMAs of one unit, with the kLPW direct loads of stage ks into buffer buf
+        // spread evenly among them when doit
+        auto mma = [&](const f32x4v (&fg)[NB], const f32x4v (&fx)[NB], const f32x4v (&hx)[NB],
+                       const f32x4v (&hg)[NB], int buf, int ks, bool doit) {
+            constexpr int EVERY = NM / kLPW;
+#pragma unroll
+            for (int i = 0; i < NM; ++i) {
+                const int s = i / (2 * NB * NB), pr = (i / (NB * NB)) & 1, m = (i / NB) % NB, n = i % NB;
+                if (pr == 0)
+                    acc[0][m][n] = __builtin_amdgcn_mfma_f32_32x32x2f32(fg[m][s], hx[n][s], acc[0][m][n], 0, 0, 0);
+                else
+                    acc[1][m][n] = __builtin_amdgcn_mfma_f32_32x32x2f32(fx[m][s], hg[n][s], acc[1][m][n], 0, 0, 0);
+                if (i % EVERY == EVERY - 1) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (doit) load_one(buf, ks, i / EVERY);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        };
+
+        wait_vm(0);   // nothing of the previous item may still count against vmcnt
+        const int pro = nsl < kST ? nsl : kST;
+        for (int q = 0; q < pro; ++q)
+            for (int l = 0; l < kLPW; ++l) load_one(q, kb + q, l);
+        wait_vm((pro - 1) * kLPW);
+        __syncthreads();
+        f32x4v pg[NB], px[NB], phx[NB], phg[NB], qg[NB], qx[NB], qhx[NB], qhg[NB];
+        frags(0, 0, pg, px, phx, phg);
+        // Stages of 4 units, the units alternating between fragment sets P and Q.  After the
+        // third unit of stage st: wait for stage st + 1 (later stages may stay in flight) and
+        // the barrier (every wave has read stage st), then stage st + kST refills stage st's
+        // buffer among the MFMAs of its fourth unit.
+        for (int st = 0; st < nsl; ++st) {
+            const int buf = st % kST;
+            frags(buf, 1, qg, qx, qhx, qhg);
+            mma(pg, px, phx, phg, 0, 0, false);
+            frags(buf, 2, pg, px, phx, phg);
+            mma(qg, qx, qhx, qhg, 0, 0, false);
+            frags(buf, 3, qg, qx, qhx, qhg);
+            mma(pg, px, phx, phg, 0, 0, false);
+            if (st + 1 < nsl) {
+                // stages issued so far: up to st + kST - 1; wait for st + 1 only
+                const int last = (st + kST - 1 < nsl - 1) ? st + kST - 1 : nsl - 1;
+                wait_vm((last - st - 1) * kLPW);
+                __syncthreads();
+                frags((st + 1) % kST, 0, pg, px, phx, phg);
+                mma(qg, qx, qhx, qhg, buf, kb + st + kST, st + kST < nsl);
+            } else {
+                mma(qg, qx, qhx, qhg, 0, 0, false);
+            }
         }
-#pragma unroll
-        for (int n = 0; n < NB; ++n) {
-            const int row = wn * WT + n * 32 + r32;
-            const int off = row * kRow + ((((h << 1) + (lane >> 5)) ^ swz8(row)) << 4);
-            hx[n] = *(const f32x4v*)(base + 2 * kArr + off);
-            hg[n] = *(const f32x4v*)(base + 3 * kArr + off);
-        }
-    };
-    // one accumulator per product (G_I X_J^T and X_I G_J^T): two independent MFMA chains
-    f32x16 acc[2][NB][NB];
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
+        __syncthreads();   // every fragment read done before the stages are reused
 #pragma unroll
         for (int m = 0; m < NB; ++m)
 #pragma unroll
-            for (int n = 0; n < NB; ++n)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) acc[q][m][n][r] = 0.f;
-    // the NM MFMAs of one unit (G_I X_J^T + X_I G_J^T), with the kLPW direct loads of stage
-    // ks into buffer buf spread evenly among them when doit
-    auto mma = [&](const f32x4v (&fg)[NB], const f32x4v (&fx)[NB], const f32x4v (&hx)[NB], const f32x4v (&hg)[NB],
-                   int buf, int ks, bool doit) {
-        constexpr int EVERY = NM / kLPW;
-#pragma unroll
-        for (int i = 0; i < NM; ++i) {
-            const int s = i / (2 * NB * NB), pr = (i / (NB * NB)) & 1, m = (i / NB) % NB, n = i % NB;
-            if (pr == 0)
-                acc[0][m][n] = __builtin_amdgcn_mfma_f32_32x32x2f32(fg[m][s], hx[n][s], acc[0][m][n], 0, 0, 0);
-            else
-                acc[1][m][n] = __builtin_amdgcn_mfma_f32_32x32x2f32(fx[m][s], hg[n][s], acc[1][m][n], 0, 0, 0);
-            if (i % EVERY == EVERY - 1) {
-                __builtin_amdgcn_sched_barrier(0);
-                if (doit) load_one(buf, ks, i / EVERY);
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        }
-    };
+            for (int n = 0; n < NB; ++n) acc[0][m][n] += acc[1][m][n];
 
-    const int pro = nsl < kST ? nsl : kST;
-    for (int q = 0; q < pro; ++q)
-        for (int l = 0; l < kLPW; ++l) load_one(q, q, l);
-    wait_vm((pro - 1) * kLPW);
-    __syncthreads();
-    f32x4v pg[NB], px[NB], phx[NB], phg[NB], qg[NB], qx[NB], qhx[NB], qhg[NB];
-    frags(0, 0, pg, px, phx, phg);
-    // Stages of 4 units, the units alternating between fragment sets P and Q.  After the
-    // third unit of stage st: wait for stage st + 1 (the only loads in flight) and the
-    // barrier (every wave has read stage st), then stage st + 2 refills stage st's buffer
-    // among the MFMAs of its fourth unit.
-    for (int st = 0; st < nsl; ++st) {
-        const int buf = st % kST;
-        // units 0, 1
-        frags(buf, 1, qg, qx, qhx, qhg);
-        mma(pg, px, phx, phg, 0, 0, false);
-        frags(buf, 2, pg, px, phx, phg);
-        mma(qg, qx, qhx, qhg, 0, 0, false);
-        // units 2, 3
-        frags(buf, 3, qg, qx, qhx, qhg);
-        mma(pg, px, phx, phg, 0, 0, false);
-        if (st + 1 < nsl) {
-            // stage st + 1 readable; the buffer of stage st is free once every wave has read
-            // unit 3 above (the barrier), and is refilled with stage st + 2
-            wait_vm(0);
+        // ---------------------------------------------------------------- split tail
+        bool finish = chunk < 0;
+        if (!finish) {
+            constexpr size_t TILE_F = (size_t)BT * BT;
+            f32x4v* wp = (f32x4v*)(sk.partial + (size_t)v * TILE_F) + (size_t)wave * NB * NB * 4 * 64 + lane;
+#pragma unroll
+            for (int m = 0; m < NB; ++m)
+#pragma unroll
+                for (int n = 0; n < NB; ++n)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        f32x4v vv = {acc[0][m][n][4 * q], acc[0][m][n][4 * q + 1], acc[0][m][n][4 * q + 2],
+                                     acc[0][m][n][4 * q + 3]};
+                        *wp = vv;
+                        wp += 64;
+                    }
+            __threadfence();
             __syncthreads();
-            frags((st + 1) % kST, 0, pg, px, phx, phg);
-            mma(qg, qx, qhx, qhg, buf, st + 2, st + 2 < nsl);
-        } else {
-            mma(qg, qx, qhx, qhg, 0, 0, false);
-        }
-    }
-
-    // epilogue: G_k = W M + B G over row <= col, mirrored; FP64 partials
-    const float wk = a.coef[0], bk = a.coef[1];
-    const bool diag = (I == J);
-    double p_tr = 0.0, p_gx = 0.0, p_mx = 0.0;
+            if (tid == 0) s_flag = atomicAdd(sk.counter + tail_tile, 1);
+            __syncthreads();
+            // each layer adds `chunks` arrivals per tail tile: the last one reduces
+            finish = ((s_flag + 1) % sk.chunks) == 0;
+            if (finish) {
+                __threadfence();
+                const f32x4v* rp = (const f32x4v*)(sk.partial + (size_t)tail_tile * sk.chunks * TILE_F) +
+                                   (size_t)wave * NB * NB * 4 * 64 + lane;
+                const size_t cstride = TILE_F / 4;
 #pragma unroll
-    for (int m = 0; m < NB; ++m) {
+                for (int m = 0; m < NB; ++m)
 #pragma unroll
-        for (int n = 0; n < NB; ++n) {
-            const int col = J * kBT + wn * WT + n * 32 + (lane & 31);
+                    for (int n = 0; n < NB; ++n)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = I * kBT + wm * WT + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                if (diag && row > col) continue;
-                const size_t off = (size_t)row * np + col;
-                const float mv = acc[0][m][n][r] + acc[1][m][n][r];
-                const float gv = a.g[off];
-                const float xv = a.x[off];
-                const float gn = fmaf(wk, mv, bk * gv);
-                a.g_out[off] = gn;
-                if (row != col) a.g_out[(size_t)col * np + row] = gn;
-                const double wgt = (row == col) ? 1.0 : 2.0;
-                if (row == col) p_tr += (double)gv;
-                p_gx += wgt * (double)gv * (double)xv;
-                p_mx += 0.5 * wgt * (double)mv * (double)xv;
+                        for (int q = 0; q < 4; ++q) {
+                            f32x4v sum = rp[0];
+                            for (int c = 1; c < sk.chunks; ++c) sum += rp[c * cstride];
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) acc[0][m][n][4 * q + e] = sum[e];
+                            rp += 64;
+                        }
             }
         }
-    }
-    p_tr = wsum(p_tr);
-    p_gx = wsum(p_gx);
-    p_mx = wsum(p_mx);
-    if (lane == 0) {
-        red[3 * wave + 0] = p_tr;
-        red[3 * wave + 1] = p_gx;
-        red[3 * wave + 2] = p_mx;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (int w = 0; w < 4; ++w) {
-            s0 += red[3 * w];
-            s1 += red[3 * w + 1];
-            s2 += red[3 * w + 2];
+
+        // ---------------------------------------------------------------- epilogue
+        if (finish) {
+            // G_k = W M + B G over row <= col, mirrored; FP64 partials
+            const float wk = a.coef[0], bk = a.coef[1];
+            const bool diag = (I == J);
+            double p_tr = 0.0, p_gx = 0.0, p_mx = 0.0;
+#pragma unroll
+            for (int m = 0; m < NB; ++m) {
+#pragma unroll
+                for (int n = 0; n < NB; ++n) {
+                    const int col = J * kBT + wn * WT + n * 32 + (lane & 31);
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int row = I * kBT + wm * WT + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                        if (diag && row > col) continue;
+                        const size_t off = (size_t)row * np + col;
+                        const float mv = acc[0][m][n][r];
+                        const float gv = a.g[off];
+                        const float xv = a.x[off];
+                        const float gn = fmaf(wk, mv, bk * gv);
+                        a.g_out[off] = gn;
+                        if (row != col) a.g_out[(size_t)col * np + row] = gn;
+                        const double wgt = (row == col) ? 1.0 : 2.0;
+                        if (row == col) p_tr += (double)gv;
+                        p_gx += wgt * (double)gv * (double)xv;
+                        p_mx += 0.5 * wgt * (double)mv * (double)xv;
+                    }
+                }
+            }
+            p_tr = wsum(p_tr);
+            p_gx = wsum(p_gx);
+            p_mx = wsum(p_mx);
+            if (lane == 0) {
+                red[3 * wave + 0] = p_tr;
+                red[3 * wave + 1] = p_gx;
+                red[3 * wave + 2] = p_mx;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+                for (int w = 0; w < 4; ++w) {
+                    s0 += red[3 * w];
+                    s1 += red[3 * w + 1];
+                    s2 += red[3 * w + 2];
+                }
+                a.parts[3 * t + 0] = s0;
+                a.parts[3 * t + 1] = s1;
+                a.parts[3 * t + 2] = s2;
+            }
         }
-        a.parts[3 * t + 0] = s0;
-        a.parts[3 * t + 1] = s1;
-        a.parts[3 * t + 2] = s2;
+        __syncthreads();   // LDS and red are reused by the next item
     }
 }
 
@@ -307,12 +383,41 @@ int adjoint_grid(int tile, int np, int* T, int* ntiles, int* per) {
     return 8 * *per;
 }
 
-hipError_t launch_adjoint(int tile, const AdjointArgs& a, hipStream_t s) {
-    const int grid = 8 * a.per;
-    if (tile == 128)
-        hipLaunchKernelGGL((k_adjoint_dl<128>), dim3(grid), dim3(256), 0, s, a);
+// Adjoint variants: 0 = 64 tiles, 2 LDS stages (64 KB, two workgroups per CU); 1 = 64
+// tiles, 4 stages (128 KB, one per CU); 2 = 128 tiles, 2 stages (128 KB, one per CU).
+// Persistent schedule: G = CUs x workgroups per CU, whole rounds, then the leftover tiles in
+// G / rem K-chunks (at most one chunk per K-stage; with fewer tiles than workgroups every
+// tile is split).
+int adjoint_tile(int variant) { return variant == 2 ? 128 : 64; }
+
+void adjoint_plan(int variant, int np, int cus, StreamK* sk) {
+    const int tile = adjoint_tile(variant);
+    const int nt = ntiles_upper(np / tile);
+    int g = cus * (variant == 0 ? 2 : 1);
+    if (g > kMaxSkGrid) g = kMaxSkGrid;
+    g -= g % 8;
+    if (g < 8) g = 8;
+    const int nsl = np / 32;
+    sk->grid = g;
+    sk->rounds = nt / g;
+    sk->tail_tiles = nt % g;
+    sk->chunks = sk->tail_tiles ? g / sk->tail_tiles : 1;
+    if (sk->chunks > nsl) sk->chunks = nsl;
+    if (sk->chunks < 1) sk->chunks = 1;
+}
+
+size_t adjoint_partial_bytes(int variant) {
+    const int tile = adjoint_tile(variant);
+    return (size_t)kMaxSkGrid * tile * tile * sizeof(float);
+}
+
+hipError_t launch_adjoint(int variant, const AdjointArgs& a, const StreamK& sk, hipStream_t s) {
+    if (variant == 2)
+        hipLaunchKernelGGL((k_adjoint_dl<128, 2>), dim3(sk.grid), dim3(256), 0, s, a, sk);
+    else if (variant == 1)
+        hipLaunchKernelGGL((k_adjoint_dl<64, 4>), dim3(sk.grid), dim3(256), 0, s, a, sk);
     else
-        hipLaunchKernelGGL((k_adjoint_dl<64>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_adjoint_dl<64, 2>), dim3(sk.grid), dim3(256), 0, s, a, sk);
     return hipGetLastError();
 }
 

@@ -150,7 +150,11 @@ struct AdjointArgs {
 hipError_t launch_pack_coef(const float* w, const float* b, const float* c, int K, float* out, hipStream_t s);
 hipError_t launch_copy_pad(const float* src, float* dst, int n, int ld, int np, int to_pad, hipStream_t s);
 int adjoint_grid(int tile, int np, int* T, int* ntiles, int* per);
-hipError_t launch_adjoint(int tile, const AdjointArgs& a, hipStream_t s);
+// adjoint variants 0..2 (k_net.hip): tile, schedule, split-K partial buffer, launch
+int adjoint_tile(int variant);
+void adjoint_plan(int variant, int np, int cus, StreamK* sk);
+size_t adjoint_partial_bytes(int variant);
+hipError_t launch_adjoint(int variant, const AdjointArgs& a, const StreamK& sk, hipStream_t s);
 hipError_t launch_reduce3(const double* parts, int nparts, float* dw, float* db, float* dc, int k, hipStream_t s);
 
 // One problem of a batched call (device copy; pointers into the batch workspace).  The

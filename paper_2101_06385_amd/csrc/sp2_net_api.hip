@@ -14,11 +14,16 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// adjoint variant for n <= 4096 (64 tiles): 0 = 2 LDS stages, two workgroups per CU;
+// 1 = 4 stages, one per CU
+constexpr int kAdjVariantSmall = 0;
+
 struct NetPlan {
-    int n, np, K, c, nck, precision, tile_main, tile_adj, scale_log2;
+    int n, np, K, c, nck, precision, tile_main, tile_adj, adj_variant, scale_log2;
     bool split;
     int T_main, nt_main, per_main, T_adj, nt_adj, per_adj;
-    size_t off_coef, off_adj_parts, off_ckpt, off_seg, off_ping, off_planes, off_g, off_xout, total;
+    size_t off_coef, off_adj_parts, off_adj_partial, off_adj_counter, off_ckpt, off_seg, off_ping, off_planes, off_g,
+        off_xout, total;
 };
 
 bool net_plan(int n, int K, int precision, int ckpt_every, NetPlan* p) {
@@ -33,9 +38,10 @@ bool net_plan(int n, int K, int precision, int ckpt_every, NetPlan* p) {
     if (p->c > K) p->c = K;
     p->nck = (K + p->c - 1) / p->c;
     p->tile_main = n <= 256 ? 64 : 128;
-    // adjoint tile: 64 until 128 tiles fill the GPU (136 tiles of 128 at n = 2048 left
+    // adjoint: 64 tiles until 128 tiles fill the GPU (136 tiles of 128 at n = 2048 left
     // half the CUs idle)
-    p->tile_adj = n <= 4096 ? 64 : 128;
+    p->adj_variant = n <= 4096 ? kAdjVariantSmall : 2;
+    p->tile_adj = adjoint_tile(p->adj_variant);
     const int m = p->tile_main > p->tile_adj ? p->tile_main : p->tile_adj;
     p->np = round_up(n, m);
     if (p->split)
@@ -49,6 +55,10 @@ bool net_plan(int n, int K, int precision, int ckpt_every, NetPlan* p) {
     off = align_up(off + sizeof(float) * 3 * K);
     p->off_adj_parts = off;
     off = align_up(off + sizeof(double) * 3 * p->nt_adj);
+    p->off_adj_partial = off;   // split-K partials of the adjoint's leftover tiles
+    off = align_up(off + adjoint_partial_bytes(p->adj_variant));
+    p->off_adj_counter = off;
+    off = align_up(off + sizeof(int) * kMaxSkGrid);
     p->off_ckpt = off;
     off = align_up(off + m2 * p->nck);
     p->off_seg = off;
@@ -182,6 +192,16 @@ int sp2_net_backward(const float* dGK, int ldg, int n, int K, const float* dW, c
     SP2_TRY(launch_pack_coef(dW, dB, dC, K, b.coef, s));
     int gc = 0;
     SP2_TRY(launch_copy_pad(dGK, b.g[gc], n, ldg, p.np, 1, s));
+    StreamK sk;
+    memset(&sk, 0, sizeof(sk));
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return SP2_EDEVICE;
+    adjoint_plan(p.adj_variant, p.np, cus, &sk);
+    sk.partial = (float*)((char*)dWork + p.off_adj_partial);
+    sk.counter = (int*)((char*)dWork + p.off_adj_counter);
+    SP2_TRY(launch_zero_ints(sk.counter, kMaxSkGrid, s));   // arrivals count modulo chunks from here
     AdjointArgs aa;
     memset(&aa, 0, sizeof(aa));
     aa.parts = b.adj_parts;
@@ -208,7 +228,7 @@ int sp2_net_backward(const float* dGK, int ldg, int n, int K, const float* dW, c
             aa.x = (k == s0) ? xs : b.seg + (size_t)(k - s0) * b.m;
             aa.g_out = b.g[gc ^ 1];
             aa.coef = b.coef + 3 * k;
-            SP2_TRY(launch_adjoint(p.tile_adj, aa, s));
+            SP2_TRY(launch_adjoint(p.adj_variant, aa, sk, s));
             SP2_TRY(launch_reduce3(b.adj_parts, p.nt_adj, ddW, ddB, ddC, k, s));
             gc ^= 1;
         }
