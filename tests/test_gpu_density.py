@@ -226,3 +226,41 @@ def test_layers_after_the_stop_do_no_work(prec):
     assert extra, "expected layers enqueued after the stop"
     assert max(extra) < 0.2 * float(np.median(ran)), (max(extra), float(np.median(ran)))
     assert info["status"] == 0
+
+
+def _sampled_check(w, d, info, rows, fro_tol):
+    assert info["status"] == sp2.SP2_OK, info["status_name"]
+    assert abs(info["trace"] - w.n_occ) <= 1e-6
+    assert np.array_equal(d[rows][:, :64], d[:64][:, rows].T)
+    d_rows = dm.dm_rows(w.q, w.eps, w.n_occ, rows)
+    assert np.abs(d[rows] - d_rows).max() <= fro_tol
+    assert abs(info["idem"]) <= 1e-6 * w.n
+
+
+def test_stress_config_16384_sampled_rows():
+    """The second size of the small-gap stress case (N = 16384, 0.2 eV gap) with default
+    options (persistent 4-wave kernel): sampled rows of D against the exact projector."""
+    w = wl.config3(n=16384, device=DEV)
+    h = torch.from_numpy(w.h).to(DEV)
+    d, info = sp2.density(h, w.n_occ)
+    assert info["kernel"] >= 2 and info["tile"] == 256
+    _sampled_check(w, d.cpu().numpy(), info, [0, 8191, 16383], 1e-3)
+
+
+def test_stress_config_8192_bf16_sampled_rows():
+    """BF16 planes on the N = 8192 stress case (the precision comparison of that case)."""
+    w = wl.config3(n=8192, device=DEV)
+    h = torch.from_numpy(w.h).to(DEV)
+    d, info = sp2.density(h, w.n_occ, precision="bf16x2")
+    _sampled_check(w, d.cpu().numpy(), info, [1, 4097, 8190], 2e-3)
+
+
+def test_stress_config_8192_fp64_sampled_rows():
+    """Plain FP64 SP2 at N = 8192 (the speed comparison of the benchmark): near-FP64 rows."""
+    w = wl.config3(n=8192, device=DEV)
+    h = torch.from_numpy(w.h).to(DEV)
+    d, info = sp2.density(h, w.n_occ, precision="fp64")
+    assert info["status"] == sp2.SP2_OK
+    rows = [2, 5000]
+    d = d.cpu().numpy()
+    assert np.abs(d[rows] - dm.dm_rows(w.q, w.eps, w.n_occ, rows)).max() <= 1e-9
