@@ -80,9 +80,11 @@ typedef struct {
                             128: (4,32,4,0) (4,64,2,0) (4,16,4,0) (4,32,2,0) (4,64,2,2) (4,32,2,4)
                           Only split modes with tiles of 128/256 use these.  FP64 mode:
                           0 = automatic, 1 = register-staged kernel, 2 / 3 / 4 = direct-to-LDS
-                          kernel (128 tiles) with (4 waves, 2 stages) / (4, 4) / (8, 4); the
-                          automatic choice (4) also serves the FP64 refinement layer of every
-                          mode; 5..7 are invalid. */
+                          kernel (128 tiles) with (4 waves, 2 stages) / (4, 4) / (8, 4),
+                          one workgroup per tile, 5 = the (8, 4) kernel on the persistent
+                          schedule (whole rounds + split-K tail; per-tile where there are
+                          fewer tiles than CUs).  The automatic choice (5, else 4) also
+                          serves the FP64 refinement layer of every mode; 6, 7 are invalid. */
 } sp2_options;
 
 typedef struct {

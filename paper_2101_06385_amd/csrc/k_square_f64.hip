@@ -65,9 +65,13 @@ __device__ inline double wsum(double v) {
 }
 
 // WN waves across the tile's columns (2: 4 waves of 64 x 64, 4: 8 waves of 64 x 32)
+// One work item: tile t over K-stages [kb, ke).  chunk < 0: the whole tile, epilogue here;
+// otherwise one K-chunk of tail tile `tail_tile`: the FP64 partial goes to slot v of
+// sk.partial and the last arriving chunk sums the chunks in order and runs the epilogue.
 template <int ST, int WN>
-__device__ __forceinline__ void f64_body(const SquareArgs& a, int t, unsigned char* __restrict__ lds,
-                                         double* __restrict__ red) {
+__device__ __forceinline__ void f64_body(const SquareArgs& a, int t, int kb, int ke, int chunk, int tail_tile,
+                                         int v, const StreamK& sk, unsigned char* __restrict__ lds,
+                                         double* __restrict__ red, int* __restrict__ s_flag) {
     static_assert(ST >= 2 && ST <= 4, "stages");
     constexpr int kNW = 2 * WN;
     constexpr int kLPW = 2 * kBPR / kNW;   // direct loads per wave per stage
@@ -80,7 +84,7 @@ __device__ __forceinline__ void f64_body(const SquareArgs& a, int t, unsigned ch
     const int wm = wave / WN, wn = wave % WN;
     const double* x = (const double*)a.x0;
     const double* src[2] = {x + (size_t)I * kBT * np, x + (size_t)J * kBT * np};
-    const int nsl = np / kBK;
+    const int nsl = ke - kb;
 
     // direct load: lane L fills bytes [16 L, 16 L + 16) of block q: panel row q * 8 + L / 8,
     // physical chunk L % 8 = logical chunk (L % 8) ^ swz8(row)
@@ -128,7 +132,7 @@ __device__ __forceinline__ void f64_body(const SquareArgs& a, int t, unsigned ch
 
     // stage q is issued by advance(q - ST + 1); the prologue plays those of 0 .. ST - 1
     const int pro = nsl < ST ? nsl : ST;
-    for (int q = 0; q < pro; ++q) issue(q, q);
+    for (int q = 0; q < pro; ++q) issue(q, kb + q);
     wait_vm((pro - 1) * kLPW);
     __syncthreads();
     f64x2 pa[kMB], pb[kNB], qa[kMB], qb[kNB];
@@ -171,11 +175,43 @@ __device__ __forceinline__ void f64_body(const SquareArgs& a, int t, unsigned ch
         mma(pa, pb);
         arrive(st + 1);
         frags((st + 1) % ST, 0, pa, pb);
-        mma_issue(qa, qb, st % ST, st + ST, st + ST < nsl);
+        mma_issue(qa, qb, st % ST, kb + st + ST, st + ST < nsl);
     }
     frags(st % ST, 1, qa, qb);
     mma(pa, pb);
     mma(qa, qb);
+
+    // ------------------------------------------------------------------- split tail
+    if (chunk >= 0) {
+        constexpr size_t TILE_D = (size_t)kBT * kBT;
+        f64x4* wp = (f64x4*)(sk.fpartial + (size_t)v * TILE_D) + (size_t)wave * kMB * kNB * 64 + lane;
+#pragma unroll
+        for (int m = 0; m < kMB; ++m)
+#pragma unroll
+            for (int n = 0; n < kNB; ++n) {
+                *wp = acc[m][n];
+                wp += 64;
+            }
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) *s_flag = atomicAdd(sk.counter + tail_tile, 1);
+        __syncthreads();
+        // each executed layer adds `chunks` arrivals per tail tile: the last one reduces
+        if (((*s_flag + 1) % sk.chunks) != 0) return;
+        __threadfence();
+        const f64x4* rp = (const f64x4*)(sk.fpartial + (size_t)tail_tile * sk.chunks * TILE_D) +
+                          (size_t)wave * kMB * kNB * 64 + lane;
+        const size_t cstride = TILE_D / 4;
+#pragma unroll
+        for (int m = 0; m < kMB; ++m)
+#pragma unroll
+            for (int n = 0; n < kNB; ++n) {
+                f64x4 sum = rp[0];
+                for (int c = 1; c < sk.chunks; ++c) sum += rp[c * cstride];
+                acc[m][n] = sum;
+                rp += 64;
+            }
+    }
 
     // ------------------------------------------------------------------- epilogue
     const double alpha = (double)a.coef[0], beta = (double)a.coef[1], gamma = (double)a.coef[2];
@@ -233,10 +269,44 @@ template <int ST, int WN>
 __global__ __launch_bounds__(128 * WN) void k_square_f64(SquareArgs a) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[ST * kStage];
     __shared__ double red[4 * WN];
+    __shared__ int s_flag;
     if (a.skip && *a.skip) return;
     const int t = xcd_tile_index(blockIdx.x, a.per, a.ntiles);
     if (t < 0) return;
-    f64_body<ST, WN>(a, t, lds, red);
+    StreamK none;
+    none.grid = 0;
+    none.rounds = 0;
+    none.tail_tiles = 0;
+    none.chunks = 1;
+    none.partial = nullptr;
+    none.counter = nullptr;
+    none.fpartial = nullptr;
+    f64_body<ST, WN>(a, t, 0, a.np / kBK, -1, 0, 0, none, lds, red, &s_flag);
+}
+
+// Persistent: sk.grid workgroups run whole rounds of tiles, then the leftover tiles cut into
+// sk.chunks K-chunks each (the same schedule as the persistent split squaring).
+template <int ST, int WN>
+__global__ __launch_bounds__(128 * WN) void k_square_f64_sk(SquareArgs a, StreamK sk) {
+    __shared__ __attribute__((aligned(16))) unsigned char lds[ST * kStage];
+    __shared__ double red[4 * WN];
+    __shared__ int s_flag;
+    if (a.skip && *a.skip) return;
+    const int G = sk.grid;
+    const int v = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);   // XCD-aware order
+    const int nsl_all = a.np / kBK;
+    const int items = sk.rounds + ((sk.tail_tiles > 0 && v < sk.tail_tiles * sk.chunks) ? 1 : 0);
+    for (int item = 0; item < items; ++item) {
+        if (item < sk.rounds) {
+            f64_body<ST, WN>(a, item * G + v, 0, nsl_all, -1, 0, v, sk, lds, red, &s_flag);
+        } else {
+            const int tail_tile = v / sk.chunks, chunk = v % sk.chunks;
+            const int kb = (int)(((long long)chunk * nsl_all) / sk.chunks);
+            const int ke = (int)(((long long)(chunk + 1) * nsl_all) / sk.chunks);
+            f64_body<ST, WN>(a, sk.rounds * G + tail_tile, kb, ke, chunk, tail_tile, v, sk, lds, red, &s_flag);
+        }
+        __syncthreads();   // LDS is reused by the next item
+    }
 }
 
 // grouped: block b of problem p (offs[p] <= b < offs[p + 1]) computes tile b - offs[p]
@@ -248,7 +318,16 @@ __global__ __launch_bounds__(128 * WN) void k_square_f64_g(const SquareArgs* __r
     const int p = find_group(offs, nprob, blockIdx.x);
     const SquareArgs a = descs[p];
     if (a.skip && *a.skip) return;
-    f64_body<ST, WN>(a, blockIdx.x - offs[p], lds, red);
+    __shared__ int s_flag;
+    StreamK none;
+    none.grid = 0;
+    none.rounds = 0;
+    none.tail_tiles = 0;
+    none.chunks = 1;
+    none.partial = nullptr;
+    none.counter = nullptr;
+    none.fpartial = nullptr;
+    f64_body<ST, WN>(a, blockIdx.x - offs[p], 0, a.np / kBK, -1, 0, 0, none, lds, red, &s_flag);
 }
 
 }  // namespace
@@ -256,6 +335,31 @@ __global__ __launch_bounds__(128 * WN) void k_square_f64_g(const SquareArgs* __r
 // grouped FP64 layer on 128 tiles (8 waves, 4 stages) over nprob problems
 hipError_t launch_square_f64_g(const SquareArgs* descs, const int* offs, int nprob, int blocks, hipStream_t s) {
     hipLaunchKernelGGL((k_square_f64_g<4, 4>), dim3(blocks), dim3(512), 0, s, descs, offs, nprob);
+    return hipGetLastError();
+}
+
+// Persistent FP64 schedule on 128 tiles: G = CUs (one 8-wave workgroup per CU), whole rounds,
+// then the leftover tiles in G / rem K-chunks (at most one per K-stage).  False when there
+// are fewer tiles than workgroups.
+bool square_f64_sk_plan(int np, int cus, StreamK* sk) {
+    const int nt = ntiles_upper(np / kBT);
+    int g = cus;
+    if (g > kMaxSkGrid) g = kMaxSkGrid;
+    g -= g % 8;
+    if (g < 8 || nt < g) return false;
+    const int nsl = np / kBK;
+    sk->grid = g;
+    sk->rounds = nt / g;
+    sk->tail_tiles = nt % g;
+    sk->chunks = sk->tail_tiles ? g / sk->tail_tiles : 1;
+    if (sk->chunks > nsl) sk->chunks = nsl;
+    return true;
+}
+
+size_t square_f64_sk_partial_bytes() { return (size_t)kMaxSkGrid * kBT * kBT * sizeof(double); }
+
+hipError_t launch_square_f64_sk(const SquareArgs& a, const StreamK& sk, hipStream_t s) {
+    hipLaunchKernelGGL((k_square_f64_sk<4, 4>), dim3(sk.grid), dim3(512), 0, s, a, sk);
     return hipGetLastError();
 }
 

@@ -584,6 +584,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_dp(SquareArgs a) {
     none.chunks = 1;
     none.partial = nullptr;
     none.counter = nullptr;
+    none.fpartial = nullptr;
     sk_body<T16, WM, WN, MB, NB, SK, ST, 0, true>(a, none, 0, t);
 }
 
@@ -603,6 +604,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_dp_g(const SquareArgs* 
     none.chunks = 1;
     none.partial = nullptr;
     none.counter = nullptr;
+    none.fpartial = nullptr;
     sk_body<T16, WM, WN, MB, NB, SK, ST, 0, true>(a, none, 0, blockIdx.x - offs[p]);
 }
 

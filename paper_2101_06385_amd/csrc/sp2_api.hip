@@ -49,7 +49,7 @@ bool read_opts(const sp2_options* o, Opts* r) {
     if (r->tile != 0 && r->tile != 64 && r->tile != 128 && r->tile != 256) return false;
     if (r->tile == 256 && !split) return false;
     if (r->kernel < 0 || (r->kernel > 1 + kSkVariants && r->kernel != 8)) return false;
-    if (r->precision == SP2_FP64 && r->kernel > 4) return false;
+    if (r->precision == SP2_FP64 && r->kernel > 5) return false;
     if (!isfinite(r->eps)) return false;
     if (r->have_bounds && !(isfinite(r->emin) && isfinite(r->emax) && r->emax > r->emin)) return false;
     return true;
@@ -62,7 +62,8 @@ struct Plan {
     int kernel;       // request: 0 = automatic, 1 = one workgroup per tile, 2.. = persistent variant - 2
     bool sk_capable;  // stream-K buffers are part of the workspace
     size_t off_init_parts, off_main_parts, off_gersh, off_dstats, off_s[2], off_p[2][2], off_s64, off_y;
-    size_t off_sk_partial, off_sk_counter, total;
+    size_t off_sk_partial, off_sk_counter, off_f64_partial, off_f64_counter, total;
+    bool f64_sk;      // persistent FP64 layer buffers reserved
 };
 
 // The persistent (whole rounds + split tail) schedule needs a tile of 128 or 256 in a
@@ -103,13 +104,38 @@ hipError_t launch_split_tile_layer(int precision, int tile, int kernel, const Sq
     return launch_square_split(precision, tile, a, s);
 }
 
-// FP64 layer: the direct-load kernel on 128 tiles (kernel 2 / 3 / 4 = its variants 0 / 1 /
-// 2, 0 = automatic), the register-staged plain kernel for 64 tiles or kernel 1.
+// FP64 layer on 128 tiles: kernel 0 (automatic) = the persistent schedule when `sk` holds a
+// feasible plan, else the per-tile direct-load kernel (8 waves); 2 / 3 / 4 = per-tile
+// variants 0 / 1 / 2; 5 = persistent (per-tile where infeasible); 1 or 64 tiles = the
+// register-staged kernel.
 constexpr int kF64AutoVariant = 2;
-hipError_t launch_f64_layer(int tile, int kernel, const SquareArgs& a, hipStream_t s) {
-    if (tile == 128 && kernel != 1) return launch_square_f64(kernel >= 2 ? kernel - 2 : kF64AutoVariant, a, s);
+hipError_t launch_f64_layer(int tile, int kernel, const SquareArgs& a, const StreamK* sk, hipStream_t s) {
+    if (tile == 128 && kernel != 1) {
+        if ((kernel == 0 || kernel == 5) && sk && sk->grid > 0) return launch_square_f64_sk(a, *sk, s);
+        return launch_square_f64(kernel >= 2 && kernel <= 4 ? kernel - 2 : kF64AutoVariant, a, s);
+    }
     return launch_square_plain(SP2_FP64, tile, a, s);
 }
+
+// Persistent FP64 plan for this device, or grid = 0 when infeasible
+StreamK f64_sk_resolve(int np, void* partial, int* counter) {
+    StreamK sk;
+    memset(&sk, 0, sizeof(sk));
+    int dev = 0, cus = 0;
+    if (!partial || !counter) return sk;
+    if (hipGetDevice(&dev) != hipSuccess) return sk;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return sk;
+    if (!square_f64_sk_plan(np, cus, &sk)) {
+        memset(&sk, 0, sizeof(sk));
+        return sk;
+    }
+    sk.fpartial = (double*)partial;
+    sk.counter = counter;
+    return sk;
+}
+
+// workspace for the persistent FP64 layer is reserved once there are enough 128 tiles
+bool f64_sk_space(int np) { return ntiles_upper(np / 128) >= 64; }
 
 int auto_tile_main(int n, bool split) {
     // split modes: 256 tiles from n = 4096 (136 tiles; measured 690 vs 624 TFLOP/s for
@@ -175,6 +201,13 @@ void make_plan(int n, const Opts& o, Plan* p) {
     if (p->sk_capable) off = align_up(off + square_sk_partial_bytes(p->tile_main, p->np));
     p->off_sk_counter = off;
     if (p->sk_capable) off = align_up(off + sizeof(int) * kMaxSkGrid);
+    // persistent FP64 layers (refinement on 128 tiles, FP64 mode on 128 tiles)
+    p->f64_sk = ((o.refine && p->tile_ref == 128) || (o.precision == SP2_FP64 && p->tile_main == 128)) &&
+                f64_sk_space(p->np);
+    p->off_f64_partial = off;
+    if (p->f64_sk) off = align_up(off + square_f64_sk_partial_bytes());
+    p->off_f64_counter = off;
+    if (p->f64_sk) off = align_up(off + sizeof(int) * kMaxSkGrid);
     p->total = off;
 }
 
@@ -416,6 +449,12 @@ static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, in
             sk.counter = (int*)(ws + p.off_sk_counter);
             SP2_TRY(launch_zero_ints(sk.counter, kMaxSkGrid, s));
         }
+        StreamK f64sk;
+        memset(&f64sk, 0, sizeof(f64sk));
+        if (p.f64_sk) {
+            f64sk = f64_sk_resolve(p.np, ws + p.off_f64_partial, (int*)(ws + p.off_f64_counter));
+            if (f64sk.grid > 0) SP2_TRY(launch_zero_ints(f64sk.counter, kMaxSkGrid, s));
+        }
         SquareArgs a;
         memset(&a, 0, sizeof(a));
         a.parts = main_parts;
@@ -469,7 +508,7 @@ static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, in
             else if (p.split)
                 SP2_TRY(launch_split_tile_layer(o.precision, p.tile_main, p.kernel, a, s));
             else if (o.precision == SP2_FP64)
-                SP2_TRY(launch_f64_layer(p.tile_main, o.kernel, a, s));
+                SP2_TRY(launch_f64_layer(p.tile_main, o.kernel, a, &f64sk, s));
             else
                 SP2_TRY(launch_square_plain(o.precision, p.tile_main, a, s));
             SP2_TRY(ev.rec(ev.sq_e[layer], s));
@@ -494,7 +533,7 @@ static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, in
             r.n_valid = p.np;
             r.n_real = n;
             r.coef = st->rcoef[0];
-            SP2_TRY(launch_f64_layer(p.tile_ref, o.precision == SP2_FP64 ? o.kernel : 0, r, s));
+            SP2_TRY(launch_f64_layer(p.tile_ref, o.precision == SP2_FP64 ? o.kernel : 0, r, &f64sk, s));
             SP2_TRY(ev.rec(ev.ref[1], s));
             r.x0 = y;
             r.s_in = y;
@@ -502,7 +541,7 @@ static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, in
             r.ld_out = ldd;
             r.n_valid = n;
             r.coef = st->rcoef[1];
-            SP2_TRY(launch_f64_layer(p.tile_ref, o.precision == SP2_FP64 ? o.kernel : 0, r, s));
+            SP2_TRY(launch_f64_layer(p.tile_ref, o.precision == SP2_FP64 ? o.kernel : 0, r, &f64sk, s));
             SP2_TRY(ev.rec(ev.ref[2], s));
         } else {
             SP2_TRY(launch_select_f64(st, S[0], S[1], o.precision == SP2_FP64, dD, ldd, n, p.np, s));
@@ -576,6 +615,10 @@ size_t sp2_square_workspace_size(int n, int precision, int tile, int kernel) {
         off = align_up(off + square_sk_partial_bytes(t, np));
         off = align_up(off + sizeof(int) * kMaxSkGrid);
     }
+    if (precision == SP2_FP64 && t == 128 && (kernel == 0 || kernel == 5) && f64_sk_space(np)) {
+        off = align_up(off + square_f64_sk_partial_bytes());
+        off = align_up(off + sizeof(int) * kMaxSkGrid);
+    }
     return off;
 }
 
@@ -586,7 +629,7 @@ int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int ker
     const bool split = precision == SP2_FP16X2 || precision == SP2_BF16X2;
     if (tile != 0 && tile != 64 && tile != 128 && !(tile == 256 && split)) return SP2_EINVAL;
     if (kernel < 0 || (kernel > 1 + kSkVariants && kernel != 8)) return SP2_EINVAL;
-    if (precision == SP2_FP64 && kernel > 4) return SP2_EINVAL;
+    if (precision == SP2_FP64 && kernel > 5) return SP2_EINVAL;
     if (scale_log2 < 0) scale_log2 = precision == SP2_FP16X2 ? 12 : 0;
     if (!split) scale_log2 = 0;
     if (scale_log2 > (precision == SP2_FP16X2 ? 14 : 60)) return SP2_EINVAL;
@@ -647,7 +690,15 @@ int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int ker
         }
     } else if (precision == SP2_FP64) {
         a.x0 = dX;
-        SP2_TRY(launch_f64_layer(t, kernel, a, s));
+        StreamK f64sk;
+        memset(&f64sk, 0, sizeof(f64sk));
+        if (t == 128 && (kernel == 0 || kernel == 5) && f64_sk_space(np)) {
+            void* part = ws + off;
+            off = align_up(off + square_f64_sk_partial_bytes());
+            f64sk = f64_sk_resolve(np, part, (int*)(ws + off));
+            if (f64sk.grid > 0) SP2_TRY(launch_zero_ints(f64sk.counter, kMaxSkGrid, s));
+        }
+        SP2_TRY(launch_f64_layer(t, kernel, a, &f64sk, s));
     } else {
         a.x0 = dX;
         SP2_TRY(launch_square_plain(precision, t, a, s));

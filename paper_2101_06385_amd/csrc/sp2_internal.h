@@ -133,8 +133,9 @@ bool tune_lookup(int kind, int precision, unsigned long long key, int* tile, int
 void tune_store(int kind, int precision, unsigned long long key, int tile, int kernel, float ms);
 struct StreamK {
     int grid, rounds, tail_tiles, chunks;
-    float* partial;
-    int* counter;
+    float* partial;     // FP32 partial tiles (split squaring, adjoint)
+    int* counter;       // arrivals per tail tile, counted modulo chunks
+    double* fpartial;   // FP64 partial tiles (FP64 layer)
 };
 
 // Arguments of the FP32 adjoint layer of the generalized-SP2 network.
@@ -191,6 +192,10 @@ hipError_t launch_square_plain(int precision, int tile, const SquareArgs& a, hip
 // FP64 layer with direct-to-LDS staging, 128 tiles (k_square_f64.hip); variant 0 or 1
 hipError_t launch_square_f64(int variant, const SquareArgs& a, hipStream_t s);
 hipError_t launch_square_f64_g(const SquareArgs* descs, const int* offs, int nprob, int blocks, hipStream_t s);
+// persistent FP64 layer (whole rounds + split-K tail), 128 tiles
+bool square_f64_sk_plan(int np, int cus, StreamK* sk);
+size_t square_f64_sk_partial_bytes();
+hipError_t launch_square_f64_sk(const SquareArgs& a, const StreamK& sk, hipStream_t s);
 hipError_t launch_square_split_g(int precision, int tile, const SquareArgs* descs, const int* offs, int nprob,
                                  int blocks, hipStream_t s);
 hipError_t launch_square_plain_g(int precision, int tile, const SquareArgs* descs, const int* offs, int nprob,

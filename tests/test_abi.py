@@ -88,7 +88,7 @@ def test_invalid_options_give_zero_workspace():
     assert sp2.workspace_size(100, sp2.options(kernel=8)) > 0
     assert sp2.workspace_size(100, sp2.options(kernel=-1)) == 0
     assert sp2.workspace_size(100, sp2.options(kernel=7, tile=128)) > 0
-    assert sp2.workspace_size(100, sp2.options(precision="fp64", kernel=5)) == 0
+    assert sp2.workspace_size(100, sp2.options(precision="fp64", kernel=6)) == 0
     assert sp2.workspace_size(100, sp2.options(precision="fp64", kernel=3)) > 0
 
 

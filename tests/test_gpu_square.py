@@ -141,7 +141,7 @@ def test_square_is_deterministic():
     assert torch.equal(y1, y2) and s1 == s2
 
 
-@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4, 5])
 def test_fp64_kernels_vs_exact(kernel):
     """The FP64 layer kernels (register-staged, direct-to-LDS variants) on a
     ragged size that spans several 128 tiles: each within the FP64 accumulation bound of
@@ -160,3 +160,26 @@ def test_fp64_kernels_vs_exact(kernel):
         bound = 2.0 * n * u * mag * abs(alpha) + 2.0 * u * (np.abs(alpha * x2) + abs(beta) * np.abs(x) + abs(gamma))
         assert np.all(np.abs(y - ref) <= bound + 1e-300), kernel
         _check_sums(y, sums)
+
+
+@pytest.mark.parametrize("kernel", [5, 4])
+def test_fp64_persistent_schedule_sampled_rows(kernel):
+    """The persistent FP64 layer (whole rounds, split-K tail; 2080 tiles of 128 at n = 8150
+    leave a tail on 256 CUs) against exact FP64 products of sampled rows, twice in a row
+    (the arrival counters carry over between launches)."""
+    n = 8150
+    rng = np.random.default_rng(11)
+    a = rng.standard_normal((n, n)) / np.sqrt(n)
+    x = (a + a.T) * 0.5
+    rows = [0, 127, 128, 4000, n - 1]
+    ref = x[rows] @ x
+    mag = np.abs(x[rows]) @ np.abs(x)
+    xt = torch.from_numpy(x).to(DEV)
+    ws = sp2.alloc_workspace(sp2.lib().sp2_square_workspace_size(n, sp2.FP64, 128, kernel), xt.device)
+    for _ in range(2):
+        y, sums = sp2.square(xt, 1.0, 0.0, 0.0, precision="fp64", tile=128, kernel=kernel, workspace=ws)
+        yr = y[rows].cpu().numpy()
+        assert np.all(np.abs(yr - ref) <= 2.0 * n * 2.0 ** -53 * mag + 1e-300)
+        assert torch.equal(y, y.T)
+        tr = float(torch.trace(y))
+        assert abs(sums[0] - tr) <= 1e-10 * abs(tr)
