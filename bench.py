@@ -69,6 +69,8 @@ def kernel_name(precision, tile, kernel):
             mb = tile // 64
             nb = tile // (32 * wn)
             return "k_square_sk<%s, 2, %d, %d, %d, %d, %d, %d>" % (t16, wn, mb, nb, sk, st, pf)
+        if kernel == 1 and tile in (128, 256):
+            return "k_square_dp<%s, 2, %d, %d, 2, 32, 2>" % (t16, 4 if tile == 256 else 2, tile // 64)
         return "k_square_split<%s, %d>" % (t16, tile)
     return "k_square_plain<%s, %d>" % ("double" if precision == "fp64" else "float", tile)
 
