@@ -290,3 +290,200 @@ def theorem_constant() -> float:
     """C = (71 + 17 sqrt 17)/32 of the appendix theorem."""
     return (71.0 + 17.0 * math.sqrt(17.0)) / 32.0
 
+
+
+# --------------------------------------------------------------------------------------
+# Accelerated Deep-NN SP2 (Sec. "Accelerated Deep-NN SP2")
+# --------------------------------------------------------------------------------------
+#: accelerated layers are used while the tracked bounds leave a distance larger than
+#: this to the fixed points (max(l, 1 - h) > ACCEL_SWITCH); Alg. 1 continues from there
+ACCEL_SWITCH = 0.01
+
+
+def quadratic_range(a: float, b: float, c: float, lo: float, hi: float):
+    """(min, max) of a x^2 + b x + c over [lo, hi]: the endpoints and, if inside, the vertex."""
+    pts = [lo, hi]
+    if a != 0.0:
+        x = -b / (2.0 * a)
+        if lo < x < hi:
+            pts.append(x)
+    vals = [a * x * x + b * x + c for x in pts]
+    return min(vals), max(vals)
+
+
+def accelerated_layer(l: float, h: float):
+    """One accelerated layer: the continuous weight sigma_n and the rescale that follows.
+
+    Reading of the section (its coefficients are given only in a script that is not
+    part of the paper): with the unoccupied eigenvalues of S_{n-1} in [0, l] and the
+    occupied ones in [h, 1] (l < h; S_0 reverses the order of H), the layer applies the
+    projection p(x) = sigma x^2 + (1 - sigma) x, i.e. W = sigma I and B = (1 - sigma) S_{n-1}
+    on X_n = S_{n-1}^2 as in Alg. 1 but with sigma real, then shifts and rescales the
+    range of p over [0, 1] back onto [0, 1].  sigma is chosen to separate the images of
+    the two intervals as far as possible (min over [h, 1] minus max over [0, l]) without
+    letting them cross.
+
+    For sigma >= 1 the rescaled map is ((x - v)/(1 - v))^2 with vertex v = (sigma - 1)/(2 sigma);
+    the separation [(h - v)^2 - max(v, l - v)^2]/(1 - v)^2 increases in v up to
+    h + l - 1 and decreases for v > l/2, so v = clamp(h + l - 1, 0, l/2).  For sigma <= -1
+    the map is the mirror image x -> 1 - q(1 - x) with the roles of l and 1 - h
+    exchanged.  The branch with the larger separation is taken (the x^2 side on a tie).
+
+    Returns (sigma, W, B_s, B_i, l_new, h_new): S_n = W X_n + B_s S_{n-1} + B_i I.
+    """
+    best = None
+    for branch in (1, -1):
+        if branch > 0:
+            v = min(max(h + l - 1.0, 0.0), l / 2.0)
+        else:
+            v = min(max(1.0 - h - l, 0.0), (1.0 - h) / 2.0)
+        sigma = branch / (1.0 - 2.0 * v)
+        # rescale: the range of p over [0, 1] is mapped onto [0, 1]
+        pmin, pmax = quadratic_range(sigma, 1.0 - sigma, 0.0, 0.0, 1.0)
+        w = sigma / (pmax - pmin)
+        bs = (1.0 - sigma) / (pmax - pmin)
+        bi = -pmin / (pmax - pmin)
+        # images of the bounding intervals under the rescaled layer
+        _, l_new = quadratic_range(w, bs, bi, 0.0, l)
+        h_new, _ = quadratic_range(w, bs, bi, h, 1.0)
+        cand = (sigma, w, bs, bi, l_new, h_new)
+        if best is None or (h_new - l_new) > (best[5] - best[4]):
+            best = cand
+    return best
+
+
+def homo_lumo_rescaled(homo: float, lumo: float, e1: float, en: float):
+    """Bounds of the rescaled spectrum of S_0: unoccupied in [0, l0], occupied in [h0, 1]."""
+    return (en - lumo) / (en - e1), (en - homo) / (en - e1)
+
+
+@dataclass
+class SP2AccResult(SP2Result):
+    accelerated: int = 0                             # layers 1..accelerated used sigma_n in R
+    sigma_c: list = field(default_factory=list)     # continuous sigma_n of layer n
+    lh: list = field(default_factory=list)           # (l, h) entering layer n
+
+
+def sp2_accelerated(h: np.ndarray, n_occ: int, homo: float, lumo: float, bounds=None, eps: float = 0.0,
+                    max_layers: int = 100, activation: Callable = square_fp64, refine: bool = True,
+                    switch: float = ACCEL_SWITCH) -> SP2AccResult:
+    """Accelerated Deep-NN SP2 on the matrix H.
+
+    Every occupied eigenvalue of H is <= homo and every unoccupied one >= lumo (an
+    interval inside the HOMO-LUMO gap, the prior knowledge the section requires).
+    Layers use `accelerated_layer` while max(l, 1 - h) > switch, then Alg. 1's own
+    sign rule; the parameter-free stopping test of Alg. 1 is applied as printed, except
+    that its second clause compares IdErr_n with IdErr_{n-2} only when the two layers
+    between them were ordinary SP2 layers (the bound behind it holds for x^2 and
+    2x - x^2).  The refinement is Eq. Refinement, as for Alg. 1.
+    """
+    h = np.asarray(h, dtype=np.float64)
+    e1, en = bounds if bounds is not None else gershgorin(h)
+    l, hh = homo_lumo_rescaled(homo, lumo, e1, en)
+    accel = 0.0 <= l < hh <= 1.0
+    s_prev = rescale(h, e1, en)                      # S_0
+    res = SP2AccResult(d=None, layers=0, converged=False, bounds=(e1, en))
+    sig = [0]
+    iderr = [float("nan")]
+    last_acc = 0
+    n = 0
+    while True:
+        n += 1
+        if n > max_layers:
+            res.layers = n - 1
+            break
+        n_s = float(np.trace(s_prev))                # Tr S_{n-1}
+        x = activation(s_prev)                       # X_n = f(S_{n-1})
+        n_x = float(np.trace(x))
+        e_n = n_s - n_x
+        res.ns.append(n_s)
+        res.nx.append(n_x)
+        res.iderr.append(e_n)
+        res.lh.append((l, hh))
+        if accel and max(l, 1.0 - hh) > switch:
+            sigma, w, bs, bi, l, hh = accelerated_layer(l, hh)
+            s_sign = 1 if sigma > 0 else -1
+            last_acc = n
+            s_new = w * x + bs * s_prev + bi * np.eye(h.shape[0])
+        else:
+            v = abs(2.0 * n_s - n_x - n_occ) - abs(n_x - n_occ) - sig[n - 1] * eps
+            s_sign = sign_with_tie(v, sig[n - 1])
+            sigma = float(s_sign)
+            s_new = s_sign * x + (1 - s_sign) * s_prev
+        res.sigma.append(s_sign)
+        res.sigma_c.append(sigma)
+        sig.append(s_sign)
+        iderr.append(e_n)
+        stop = e_n <= 0.0 or (n > 2 and n >= last_acc + 3 and sig[n - 1] != sig[n - 2]
+                               and e_n > STOP_FACTOR * iderr[n - 2] ** 2)
+        if stop:
+            res.layers = n
+            res.converged = True
+            break
+        s_prev = s_new
+    res.accelerated = min(last_acc, res.layers)
+    res.s_last = s_prev
+    last = sig[res.layers - 1] if res.converged else sig[res.layers]
+    res.first_sign = -last if last != 0 else 1
+    res.d = refinement(s_prev, res.first_sign) if refine else s_prev.copy()
+    return res
+
+
+def sp2_eigen_accelerated(lam0: np.ndarray, n_occ: int, l0: float, h0: float, eps: float = 0.0,
+                          max_layers: int = 100, switch: float = ACCEL_SWITCH) -> SP2AccResult:
+    """`sp2_accelerated` on the eigenvalues of S_0 (each layer is a quadratic in S_{n-1},
+    so the eigenvalues follow the scalar maps).  FP64, O(N m).  `d` holds the refined
+    eigenvalues."""
+    lam = np.asarray(lam0, dtype=np.float64).copy()
+    l, hh = l0, h0
+    accel = 0.0 <= l < hh <= 1.0
+    res = SP2AccResult(d=None, layers=0, converged=False)
+    sig = [0]
+    iderr = [float("nan")]
+    last_acc = 0
+    n = 0
+    while True:
+        n += 1
+        if n > max_layers:
+            res.layers = n - 1
+            break
+        n_s = float(np.sum(lam))
+        x = lam * lam
+        n_x = float(np.sum(x))
+        e_n = n_s - n_x
+        res.ns.append(n_s)
+        res.nx.append(n_x)
+        res.iderr.append(e_n)
+        res.lh.append((l, hh))
+        if accel and max(l, 1.0 - hh) > switch:
+            sigma, w, bs, bi, l, hh = accelerated_layer(l, hh)
+            s_sign = 1 if sigma > 0 else -1
+            last_acc = n
+            new = w * x + bs * lam + bi
+        else:
+            v = abs(2.0 * n_s - n_x - n_occ) - abs(n_x - n_occ) - sig[n - 1] * eps
+            s_sign = sign_with_tie(v, sig[n - 1])
+            sigma = float(s_sign)
+            new = x if s_sign > 0 else 2.0 * lam - x
+        res.sigma.append(s_sign)
+        res.sigma_c.append(sigma)
+        sig.append(s_sign)
+        iderr.append(e_n)
+        stop = e_n <= 0.0 or (n > 2 and n >= last_acc + 3 and sig[n - 1] != sig[n - 2]
+                               and e_n > STOP_FACTOR * iderr[n - 2] ** 2)
+        if stop:
+            res.layers = n
+            res.converged = True
+            break
+        lam = new
+    res.accelerated = min(last_acc, res.layers)
+    res.s_last = lam
+    last = sig[res.layers - 1] if res.converged else sig[res.layers]
+    res.first_sign = -last if last != 0 else 1
+    if res.first_sign > 0:
+        y = lam * lam
+        res.d = 2.0 * y - y * y
+    else:
+        y = 2.0 * lam - lam * lam
+        res.d = y * y
+    return res

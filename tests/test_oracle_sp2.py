@@ -295,3 +295,167 @@ def test_network_with_sp2_coefficients_reproduces_alg1_chain():
     wts, bs, cs = net.sp2_branch_coefficients(res.sigma[: res.layers - 1])
     chain = net.forward_matrix(s0, wts, bs, cs)[-1]
     assert np.abs(chain - res.s_last).max() < 1e-12
+
+
+# ----------------------------------------------------------------------------- accelerated SP2
+def _brute_separation(sigma, l, h, k=4001):
+    """Separation of the images of [0, l] and [h, 1] under p(x) = sigma x^2 + (1 - sigma) x
+    rescaled by its range over [0, 1], all by dense sampling."""
+    xs = np.linspace(0.0, 1.0, 20 * k + 1)
+    p = lambda x: sigma * x * x + (1.0 - sigma) * x
+    pr = p(xs)
+    lo, hi = pr.min(), pr.max()
+    img_l = (p(np.linspace(0.0, l, k)) - lo) / (hi - lo)
+    img_h = (p(np.linspace(h, 1.0, k)) - lo) / (hi - lo)
+    return img_h.min() - img_l.max()
+
+
+def test_accelerated_layer_maximizes_separation_brute_force():
+    """Sec. Accelerated Deep-NN SP2: sigma_n in R is chosen for the widest HOMO-LUMO
+    separation after the rescale, without crossing; a grid over sigma (both signs,
+    |sigma| in (0, 400]) finds nothing better than the closed form."""
+    rng = np.random.default_rng(11)
+    cases = [(0.3, 0.9), (0.1, 0.2), (0.45, 0.55), (0.8, 0.95), (0.02, 0.98), (0.5, 0.5001)]
+    for _ in range(14):
+        a, b = np.sort(rng.uniform(0.0, 1.0, 2))
+        cases.append((float(a), float(b)))
+    mags = np.concatenate([np.linspace(0.01, 1.0, 100), np.geomspace(1.0, 400.0, 1500)])
+    grid = np.concatenate([-mags[::-1], mags])
+    for l, h in cases:
+        sigma, w, bs, bi, l1, h1 = sp2.accelerated_layer(l, h)
+        assert abs(sigma) >= 1.0
+        got = _brute_separation(sigma, l, h)
+        assert got > 0.0
+        assert abs(got - (h1 - l1)) < 1e-6 * max(1.0, h1 - l1) + 1e-7
+        best = max(_brute_separation(s, l, h, k=801) for s in grid)
+        assert got >= best - 1e-6, (l, h, sigma, got, best)
+
+
+def test_accelerated_layer_is_rescaled_onto_unit_interval():
+    """The rescaled layer maps [0, 1] onto exactly [0, 1] and equals the projection
+    sigma x^2 + (1 - sigma) x up to the affine rescale."""
+    rng = np.random.default_rng(12)
+    xs = np.linspace(0.0, 1.0, 100001)
+    for _ in range(30):
+        l, h = np.sort(rng.uniform(0.0, 1.0, 2))
+        sigma, w, bs, bi, _, _ = sp2.accelerated_layer(float(l), float(h))
+        y = w * xs * xs + bs * xs + bi
+        assert abs(y.min()) < 1e-9 and abs(y.max() - 1.0) < 1e-9
+        p = sigma * xs * xs + (1.0 - sigma) * xs
+        ys = (p - p.min()) / (p.max() - p.min())
+        assert np.abs(ys - y).max() < 1e-9
+
+
+def test_accelerated_layer_tie_is_the_sp2_square():
+    """With the gap centred at 1/2 neither branch is shifted: Alg. 1's X^2 layer
+    (W = I, B = 0) is returned, and the bounds follow x -> x^2."""
+    sigma, w, bs, bi, l1, h1 = sp2.accelerated_layer(0.3, 0.7)
+    assert (sigma, w, bs, bi) == (1.0, 1.0, 0.0, 0.0)
+    assert abs(l1 - 0.09) < 1e-15 and abs(h1 - 0.49) < 1e-15
+
+
+def _acc_cases():
+    out = []
+    for seed, n, n_occ, homo, lumo in ((21, 120, 30, -1.0, 1.0), (22, 150, 110, 5.0, 5.3),
+                                       (23, 100, 10, -14.0, -13.9), (24, 160, 80, -0.05, 0.05)):
+        out.append(wl.gapped(seed, n, n_occ, occ_lo=-20.0, homo=homo, lumo=lumo, virt_hi=20.0))
+    return out
+
+
+@pytest.mark.parametrize("exact_bounds", [False, True])
+def test_sp2_accelerated_reaches_exact_density_in_fewer_layers(exact_bounds):
+    for w in _acc_cases():
+        bounds = (float(w.eps[0]), float(w.eps[-1])) if exact_bounds else None
+        ref = dm.dm_construct(w.q, w.eps, w.n_occ)
+        acc = sp2.sp2_accelerated(w.h, w.n_occ, w.homo, w.lumo, bounds=bounds)
+        std = sp2.sp2_alg1(w.h, w.n_occ, bounds=bounds)
+        assert acc.converged and acc.accelerated > 0
+        assert np.linalg.norm(acc.d - ref) < 1e-9
+        assert abs(np.trace(acc.d) - w.n_occ) < 1e-9
+        assert acc.layers < std.layers
+
+
+def test_sp2_accelerated_matches_eigenvalue_recursion():
+    """Each layer is a quadratic in S_{n-1}: the matrix run and the run on the
+    eigenvalues of S_0 have the same history."""
+    for w in _acc_cases():
+        e1, en = sp2.gershgorin(w.h)
+        acc = sp2.sp2_accelerated(w.h, w.n_occ, w.homo, w.lumo)
+        lam0 = (en - w.eps) / (en - e1)
+        l0, h0 = sp2.homo_lumo_rescaled(w.homo, w.lumo, e1, en)
+        sc = sp2.sp2_eigen_accelerated(lam0, w.n_occ, l0, h0)
+        assert sc.layers == acc.layers and sc.accelerated == acc.accelerated
+        assert sc.sigma == acc.sigma
+        k = acc.accelerated
+        assert np.allclose(sc.sigma_c, acc.sigma_c, rtol=1e-12)
+        assert np.allclose(sc.iderr[:k + 3], acc.iderr[:k + 3], rtol=1e-6, atol=1e-9)
+
+
+def test_sp2_accelerated_bounds_enclose_and_track_the_gap_states():
+    """Invariant of the tracked bounds: unoccupied eigenvalues stay in [0, l], occupied
+    in [h, 1], and with exact HOMO/LUMO values h is the HOMO state's own eigenvalue."""
+    for w in _acc_cases():
+        e1, en = sp2.gershgorin(w.h)
+        lam = (en - w.eps) / (en - e1)           # index n_occ - 1: HOMO, n_occ: LUMO
+        l, h = sp2.homo_lumo_rescaled(w.homo, w.lumo, e1, en)
+        while max(l, 1.0 - h) > sp2.ACCEL_SWITCH:
+            occ, un = lam[:w.n_occ], lam[w.n_occ:]
+            assert un.max() <= l + 1e-12 and occ.min() >= h - 1e-12
+            assert abs(lam[w.n_occ - 1] - h) < 1e-12 and abs(lam[w.n_occ] - l) < 1e-9 + 1e-9 * l
+            _, wc, bs, bi, l, h = sp2.accelerated_layer(l, h)
+            lam = wc * lam * lam + bs * lam + bi
+            assert lam.min() > -1e-12 and lam.max() < 1.0 + 1e-12
+
+
+def test_sp2_accelerated_without_valid_gap_is_alg1():
+    """HOMO/LUMO values that do not lie inside the rescaled interval leave Alg. 1 unchanged."""
+    w = _acc_cases()[0]
+    std = sp2.sp2_alg1(w.h, w.n_occ)
+    for homo, lumo in ((1.0, -1.0), (-1e6, 1e6)):
+        acc = sp2.sp2_accelerated(w.h, w.n_occ, homo, lumo)
+        assert acc.accelerated == 0
+        assert acc.layers == std.layers and acc.sigma == std.sigma
+        assert np.array_equal(acc.d, std.d)
+
+
+def test_acceleration_example_layer_ratio():
+    """The section's example converges in 17 instead of 28 layers (100 x 100, N_occ = 10;
+    the matrix itself is not given, so the counts are parity unpinned).  On seeded
+    100 x 100 Hamiltonians with N_occ = 10 and a uniform spectrum the ratio is similar."""
+    g = golden()
+    n, n_occ = int(g["accelerated_example_n"]), int(g["accelerated_example_n_occ"])
+    paper = g["accelerated_example_layers"] / g["standard_example_layers"]
+    for seed in (31, 32, 33):
+        rng = np.random.default_rng(seed)
+        eps = np.sort(rng.uniform(-1.0, 1.0, n))
+        lam0 = (1.0 - eps) / 2.0
+        acc = sp2.sp2_eigen_accelerated(lam0, n_occ, lam0[n_occ], lam0[n_occ - 1])
+        std = sp2.sp2_eigen(lam0, n_occ)
+        ratio = acc.layers / std.layers
+        assert abs(ratio - paper) < 0.15, (seed, acc.layers, std.layers)
+        d = np.zeros(n)
+        d[:n_occ] = 1.0
+        assert np.abs(acc.d - d).max() < 1e-12
+
+
+def test_sp2_accelerated_tiny_systems_brute_force():
+    """Brute force on tiny spectra (n = 2..5, gaps down to 1e-6, anywhere in [0, 1]):
+    the accelerated run returns the exact step function every time.  Here IdErr is
+    small while layers are still accelerated; an alternation test taken across them
+    would stop early on some of these spectra."""
+    rng = np.random.default_rng(41)
+    for _ in range(800):
+        n = int(rng.integers(2, 6))
+        n_occ = int(rng.integers(1, n))
+        gap = 10 ** rng.uniform(-6, -0.5)
+        c = rng.uniform(0.01 + gap, 0.99 - gap)
+        l, h = c - gap / 2, c + gap / 2
+        un = np.sort(rng.uniform(0.0, l, n - n_occ))
+        un[-1] = l
+        oc = np.sort(rng.uniform(h, 1.0, n_occ))
+        oc[0] = h
+        lam0 = np.concatenate([un, oc])
+        res = sp2.sp2_eigen_accelerated(lam0, n_occ, l, h)
+        expect = (np.arange(n) >= n - n_occ).astype(float)
+        assert res.converged
+        assert np.abs(res.d - expect).max() < 1e-9, (n, n_occ, l, h, res.layers)
