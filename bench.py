@@ -117,6 +117,7 @@ def main():
     ap.add_argument("--precision", default="fp16x2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-accel", action="store_true", help="skip the accelerated Deep-NN SP2 leg")
     ap.add_argument("--gen-device", default="cuda", help="where the QR of the workload generator runs")
     ap.add_argument("--workload", default="density", choices=["density", "batched", "net"],
                     help="density: the N=8192 headline (default); batched: 64 Hamiltonians of uneven "
@@ -245,6 +246,43 @@ def main():
     else:
         d64 = None
 
+    dacc = d64a = None
+    if not args.no_accel:
+        # Accelerated Deep-NN SP2 on the same H with its HOMO/LUMO values as the prior
+        # knowledge the method needs (as from a previous call in a molecular-dynamics run)
+        gap = (w.homo, w.lumo)
+        dacc = torch.empty_like(h)
+        oacc = sp2.options(args.precision, gap=gap)
+        wsacc = sp2.alloc_workspace(sp2.workspace_size(n, oacc), dev)
+        sp2.density(h, w.n_occ, precision=args.precision, out=dacc, workspace=wsacc, gap=gap)      # warm
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            _, iacc = sp2.density(h, w.n_occ, precision=args.precision, out=dacc, workspace=wsacc, gap=gap)
+        torch.cuda.synchronize()
+        ttda = (time.perf_counter() - t1) * 1e3 / args.steps
+        acc_out = {"time_to_d_ms": round(ttda, 3), "layers": iacc["layers"], "accelerated_layers": iacc["accelerated"],
+                   "status": iacc["status_name"], "trace_error": abs(iacc["trace"] - w.n_occ),
+                   "speedup_vs_plain": round(ms_per_step / ttda, 3), "homo_lumo": list(gap)}
+        log("accelerated: time-to-D %.2f ms, layers %d (%d accelerated), %s" % (ttda, iacc["layers"],
+                                                                             iacc["accelerated"],
+                                                                             iacc["status_name"]))
+        if not args.no_fp64:
+            o64a = sp2.options("fp64", gap=gap)
+            ws64a = sp2.alloc_workspace(sp2.workspace_size(n, o64a), dev)
+            d64a = torch.empty_like(h)
+            sp2.density(h, w.n_occ, precision="fp64", out=d64a, workspace=ws64a, gap=gap)      # warm
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, i64a = sp2.density(h, w.n_occ, precision="fp64", out=d64a, workspace=ws64a, gap=gap)
+            torch.cuda.synchronize()
+            ttd64a = (time.perf_counter() - t1) * 1e3
+            acc_out["fp64"] = {"time_to_d_ms": round(ttd64a, 3), "layers": i64a["layers"],
+                               "status": i64a["status_name"], "speedup_mixed_vs_fp64": round(ttd64a / ttda, 3)}
+            log("accelerated fp64: time-to-D %.1f ms, layers %d" % (ttd64a, i64a["layers"]))
+            del ws64a
+        out["accelerated"] = acc_out
+
     if not args.no_cpu_baseline:
         # CPU leg: the oracle (test infrastructure) on a bounded sample, plus the exact
         # projector for the accuracy of the GPU results.
@@ -275,6 +313,10 @@ def main():
         if d64 is not None:
             acc["fro_error_fp64"] = float(np.linalg.norm(d64.cpu().numpy() - d_ref))
         out["accuracy"] = acc
+        if dacc is not None:
+            out["accelerated"]["fro_error"] = float(np.linalg.norm(dacc.cpu().numpy() - d_ref))
+            if "fp64" in out["accelerated"]:
+                out["accelerated"]["fp64"]["fro_error"] = float(np.linalg.norm(d64a.cpu().numpy() - d_ref))
         log("accuracy: %s" % acc)
     print(json.dumps(out), flush=True)
 

@@ -85,6 +85,22 @@ typedef struct {
                           schedule (whole rounds + split-K tail; per-tile where there are
                           fewer tiles than CUs).  The automatic choice (5, else 4) also
                           serves the FP64 refinement layer of every mode; 6, 7 are invalid. */
+    int accelerate;    /* nonzero: accelerated Deep-NN SP2 (Sec. Accelerated Deep-NN SP2).  With
+                          the occupied eigenvalues of S_{n-1} known to lie in [h, 1] and the
+                          unoccupied ones in [0, l] (from homo, lumo below and the spectral
+                          bounds), each layer uses a real weight sigma_n = +-1/(1 - 2v) with
+                          the shift-and-rescale that maps its projection back onto [0, 1]:
+                          S_n = ((S - vI)/(1 - v))^2 or I - (((1 - v)I - S)/(1 - v))^2, v and
+                          the branch chosen for the widest rescaled HOMO-LUMO separation
+                          without crossing.  Once max(l, 1 - h) <= 0.01 the layers of Alg. 1
+                          continue; its alternation stopping test is taken only across two
+                          such layers.  If homo/lumo do not rescale into 0 <= l < h <= 1 no
+                          layer is accelerated (sp2_info.accelerated = 0).  Single-problem
+                          calls only (the batched call rejects it). */
+    double homo, lumo; /* with accelerate: every occupied eigenvalue of H is <= homo and every
+                          unoccupied one >= lumo, homo < lumo (an interval inside the
+                          HOMO-LUMO gap, e.g. from a previous call); values outside the true
+                          gap can make the result wrong, which the final check reports */
 } sp2_options;
 
 typedef struct {
@@ -97,7 +113,7 @@ typedef struct {
     int kernel;            /* squaring schedule used: 1 = one workgroup per tile (also every
                               FP32/FP64 run), 8 = the register-staged per-tile kernel,
                               2 + v = persistent schedule, variant v */
-    int reserved;
+    int accelerated;       /* number of accelerated layers (they are layers 1..accelerated) */
     double emin, emax;     /* spectral bounds used */
     double trace;          /* Tr D */
     double idem;           /* Tr D - ||D||_F^2  (= Tr[D - D^2] for symmetric D) */
@@ -107,6 +123,8 @@ typedef struct {
     double iderr[SP2_MAX_LAYERS];       /* IdErr_n = Tr[S_{n-1} - S_{n-1}^2] */
     double ns[SP2_MAX_LAYERS];          /* N_S entering layer n: Tr S_{n-1} */
     double nx[SP2_MAX_LAYERS];          /* N_X of layer n: Tr X_n = ||S_{n-1}||_F^2 */
+    double sigma_c[SP2_MAX_LAYERS];     /* real weight sigma_n of layer n: sigma_n itself on
+                                           layers of Alg. 1, +-1/(1 - 2v) on accelerated ones */
 } sp2_info;
 
 /* Fill *opt with the defaults listed above. */

@@ -50,8 +50,8 @@ __device__ inline void block_sum(double (&v)[C], double* sh /* C * kThreads */) 
 }
 
 struct StateParams {
-    int n, n_occ, np, max_layers, precision, tile, have_bounds, want_energy;
-    double eps, tol_tr, tol_id, emin, emax;
+    int n, n_occ, np, max_layers, precision, tile, have_bounds, want_energy, accel;
+    double eps, tol_tr, tol_id, emin, emax, homo, lumo;
 };
 
 __global__ void k_state_init(DevState* st, StateParams p) {
@@ -61,6 +61,7 @@ __global__ void k_state_init(DevState* st, StateParams p) {
         st->iderr[i] = 0.0;
         st->ns[i] = 0.0;
         st->nx[i] = 0.0;
+        st->sigma_c[i] = 0.0;
     }
     if (t == 0) {
         st->n = p.n;
@@ -91,6 +92,12 @@ __global__ void k_state_init(DevState* st, StateParams p) {
         st->trace_d = 0.0;
         st->frob_d = 0.0;
         st->energy = 0.0;
+        st->accel = p.accel;
+        st->acc_layers = 0;
+        st->homo = p.homo;
+        st->lumo = p.lumo;
+        st->acc_l = 0.0;
+        st->acc_h = 1.0;
     }
 }
 
@@ -268,6 +275,44 @@ __device__ __forceinline__ void init_body(const double* __restrict__ h, int ldh,
 // so IdErr_n = Tr[S_{n-1} - S_{n-1}^2] is known before X_n is formed, and layer n's
 // kernels receive sigma_n as coefficients (or a skip flag once a test has held).
 // ---------------------------------------------------------------------------------
+// Accelerated layers stop once both tracked bounds are this close to their fixed points.
+constexpr double kAccSwitch = 0.01;
+
+// One accelerated layer (Sec. Accelerated Deep-NN SP2) from the bounds l < h of the
+// unoccupied / occupied eigenvalues of S_{n-1} in [0, 1].  The x^2 side applies
+// ((x - v)/(1 - v))^2: the images of [0, l] and [h, 1] are [0, (l - v)^2/(1 - v)^2] and
+// [(h - v)^2/(1 - v)^2, 1] for 0 <= v <= l/2, and their separation peaks at
+// v = h + l - 1, hence v = clamp(h + l - 1, 0, l/2).  The 2x - x^2 side is its mirror image
+// 1 - ((1 - w - x)/(1 - w))^2 with w = clamp(1 - h - l, 0, (1 - h)/2).  The wider
+// separation wins (the x^2 side on a tie).  Writes Y = a X^2 + b X + c I, the real
+// weight sigma_n = +-1/(1 - 2v) and the bounds after the layer.
+__device__ inline void accelerated_choice(double l, double h, int* sgn, double* a, double* b, double* c,
+                                          double* sigma, double* l1, double* h1) {
+    const double v = fmin(fmax(h + l - 1.0, 0.0), 0.5 * l);
+    const double dv = 1.0 - v;
+    const double ld = (l - v) * (l - v) / (dv * dv), hd = (h - v) * (h - v) / (dv * dv);
+    const double w = fmin(fmax(1.0 - h - l, 0.0), 0.5 * (1.0 - h));
+    const double dw = 1.0 - w;
+    const double lu = 1.0 - (dw - l) * (dw - l) / (dw * dw), hu = 1.0 - (dw - h) * (dw - h) / (dw * dw);
+    if (hd - ld >= hu - lu) {
+        *sgn = 1;
+        *a = 1.0 / (dv * dv);
+        *b = -2.0 * v / (dv * dv);
+        *c = v * v / (dv * dv);
+        *sigma = 1.0 / (1.0 - 2.0 * v);
+        *l1 = ld;
+        *h1 = hd;
+    } else {
+        *sgn = -1;
+        *a = -1.0 / (dw * dw);
+        *b = 2.0 / dw;
+        *c = 0.0;
+        *sigma = -1.0 / (1.0 - 2.0 * w);
+        *l1 = lu;
+        *h1 = hu;
+    }
+}
+
 __device__ __forceinline__ void control_body(DevState* st, const double* __restrict__ parts,
                                                       int nparts, int stride, int layer,
                                                       volatile int* __restrict__ host_flag) {
@@ -300,17 +345,46 @@ __device__ __forceinline__ void control_body(DevState* st, const double* __restr
     } else if (n > st->max_layers) {
         stop = true;   // S_{max_layers} is refined; status set by the final check
     } else {
-        const double occ = (double)st->n_occ;
-        const double val = fabs(2.0 * n_s - n_x - occ) - fabs(n_x - occ) - sp * st->eps;
-        int s = val > 0.0 ? 1 : (val < 0.0 ? -1 : (sp != 0 ? -sp : 1));
+        if (n == 1 && st->accel) {
+            // rescaled bounds of S_0 = (emax I - H)/(emax - emin): the order is reversed
+            const double span = st->emax - st->emin;
+            const double l0 = (st->emax - st->lumo) / span, h0 = (st->emax - st->homo) / span;
+            if (0.0 <= l0 && l0 < h0 && h0 <= 1.0) {
+                st->acc_l = l0;
+                st->acc_h = h0;
+            } else {
+                st->accel = 0;
+            }
+        }
+        int s;
+        double ca, cb, cc, sc;
+        if (st->accel && fmax(st->acc_l, 1.0 - st->acc_h) > kAccSwitch) {
+            double l1, h1;
+            accelerated_choice(st->acc_l, st->acc_h, &s, &ca, &cb, &cc, &sc, &l1, &h1);
+            st->acc_l = l1;
+            st->acc_h = h1;
+            st->acc_layers = n;
+        } else {
+            const double occ = (double)st->n_occ;
+            const double val = fabs(2.0 * n_s - n_x - occ) - fabs(n_x - occ) - sp * st->eps;
+            s = val > 0.0 ? 1 : (val < 0.0 ? -1 : (sp != 0 ? -sp : 1));
+            ca = s > 0 ? 1.0 : -1.0;
+            cb = s > 0 ? 0.0 : 2.0;
+            cc = 0.0;
+            sc = (double)s;
+        }
         st->sigma[n] = (signed char)s;
+        st->sigma_c[n] = sc;
+        // the alternation test bounds IdErr_n by the two layers before it; it is taken
+        // only when both were layers of Alg. 1
         if (e <= 0.0) conv = true;
-        else if (n > 2 && st->sigma[n - 1] != st->sigma[n - 2] && e > 4.5 * st->iderr[n - 2] * st->iderr[n - 2])
+        else if (n > 2 && n >= st->acc_layers + 3 && st->sigma[n - 1] != st->sigma[n - 2] &&
+                 e > 4.5 * st->iderr[n - 2] * st->iderr[n - 2])
             conv = true;
         if (!conv) {
-            st->coef[0] = s > 0 ? 1.f : -1.f;
-            st->coef[1] = s > 0 ? 0.f : 2.f;
-            st->coef[2] = 0.f;
+            st->coef[0] = (float)ca;
+            st->coef[1] = (float)cb;
+            st->coef[2] = (float)cc;
             st->skip = 0;
             st->layers = n;
             st->ran = n;
@@ -576,6 +650,9 @@ hipError_t launch_state_init(DevState* st, const DevState& in, hipStream_t s) {
     p.tol_id = in.tol_id;
     p.emin = in.emin;
     p.emax = in.emax;
+    p.accel = in.accel;
+    p.homo = in.homo;
+    p.lumo = in.lumo;
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(kThreads), 0, s, st, p);
     return hipGetLastError();
 }

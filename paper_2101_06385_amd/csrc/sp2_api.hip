@@ -22,7 +22,8 @@ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 struct Opts {
     int precision, max_layers, have_bounds, refine, scale_log2, want_energy, tile, kernel;
     int tile_ref;   // FP64 refinement tile, 0 = by size (set only by the batched path)
-    double eps, emin, emax;
+    int accelerate;
+    double eps, emin, emax, homo, lumo;
 };
 
 bool read_opts(const sp2_options* o, Opts* r) {
@@ -40,6 +41,10 @@ bool read_opts(const sp2_options* o, Opts* r) {
     r->eps = o->eps;
     r->emin = o->emin;
     r->emax = o->emax;
+    r->accelerate = o->accelerate != 0;
+    r->homo = o->homo;
+    r->lumo = o->lumo;
+    if (r->accelerate && !(isfinite(r->homo) && isfinite(r->lumo) && r->homo < r->lumo)) return false;
     if (r->precision < SP2_FP64 || r->precision > SP2_BF16X2) return false;
     const bool split = r->precision == SP2_FP16X2 || r->precision == SP2_BF16X2;
     r->scale_log2 = o->scale_log2 < 0 ? (r->precision == SP2_FP16X2 ? 12 : 0) : o->scale_log2;
@@ -230,7 +235,9 @@ void fill_info(const DevState& st, const Plan* p, sp2_info* info) {
         info->iderr[k - 1] = st.iderr[k];
         info->ns[k - 1] = st.ns[k];
         info->nx[k - 1] = st.nx[k];
+        info->sigma_c[k - 1] = st.sigma_c[k];
     }
+    info->accelerated = st.acc_layers;
     if (p) {
         StreamK sk;
         int variant = 0;
@@ -382,6 +389,9 @@ static DevState initial_state(int n, int n_occ, double tol, const Opts& o, const
     init.tol_id = tol > 0 ? tol : 1e-6 * n;
     init.emin = o.have_bounds ? o.emin : 0.0;
     init.emax = o.have_bounds ? o.emax : 1.0;
+    init.accel = o.accelerate;
+    init.homo = o.homo;
+    init.lumo = o.lumo;
     init.status = SP2_OK;
     return init;
 }
@@ -771,6 +781,7 @@ bool batch_opts(const sp2_options* opt, Opts* o) {
     if (!read_opts(opt, o)) return false;
     if (o->precision == SP2_FP64) return false;   // the batched path keeps FP32 state
     if (o->have_bounds) return false;             // per-problem Gershgorin bounds only
+    if (o->accelerate) return false;              // HOMO/LUMO values are per problem
     o->refine = 1;                                // the batched sequence always refines
     return true;
 }

@@ -36,6 +36,12 @@ struct DevState {
     double iderr[SP2_MAX_LAYERS + 1];
     double ns[SP2_MAX_LAYERS + 1];
     double nx[SP2_MAX_LAYERS + 1];
+    // accelerated layers (Sec. Accelerated Deep-NN SP2)
+    int accel;          // 1 while accelerated layers may still be chosen
+    int acc_layers;     // index of the last accelerated layer (0: none)
+    double homo, lumo;  // caller's interval inside the gap (energies)
+    double acc_l, acc_h;  // unoccupied eigenvalues of S_{n-1} in [0, acc_l], occupied in [acc_h, 1]
+    double sigma_c[SP2_MAX_LAYERS + 1];
 };
 
 // Upper-triangle tile enumeration shared by every kernel that works on (I <= J) tiles.

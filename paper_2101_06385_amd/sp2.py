@@ -35,6 +35,9 @@ class Options(ctypes.Structure):
         ("want_energy", ctypes.c_int),
         ("tile", ctypes.c_int),
         ("kernel", ctypes.c_int),
+        ("accelerate", ctypes.c_int),
+        ("homo", ctypes.c_double),
+        ("lumo", ctypes.c_double),
     ]
 
 
@@ -47,7 +50,7 @@ class Info(ctypes.Structure):
         ("n_padded", ctypes.c_int),
         ("tile", ctypes.c_int),
         ("kernel", ctypes.c_int),
-        ("reserved", ctypes.c_int),
+        ("accelerated", ctypes.c_int),
         ("emin", ctypes.c_double),
         ("emax", ctypes.c_double),
         ("trace", ctypes.c_double),
@@ -58,6 +61,7 @@ class Info(ctypes.Structure):
         ("iderr", ctypes.c_double * MAX_LAYERS),
         ("ns", ctypes.c_double * MAX_LAYERS),
         ("nx", ctypes.c_double * MAX_LAYERS),
+        ("sigma_c", ctypes.c_double * MAX_LAYERS),
     ]
 
 
@@ -153,7 +157,9 @@ def _prec(p) -> int:
 
 
 def options(precision="fp16x2", max_layers=100, eps=0.0, bounds=None, refine=True, scale_log2=-1,
-            want_energy=False, tile=0, kernel=0) -> Options:
+            want_energy=False, tile=0, kernel=0, gap=None) -> Options:
+    """sp2_options; `gap` = (homo, lumo) selects accelerated layers (an interval inside the
+    HOMO-LUMO gap of H)."""
     o = Options()
     lib().sp2_default_options(ctypes.byref(o))
     o.precision = _prec(precision)
@@ -167,6 +173,9 @@ def options(precision="fp16x2", max_layers=100, eps=0.0, bounds=None, refine=Tru
     o.want_energy = 1 if want_energy else 0
     o.tile = int(tile)
     o.kernel = int(kernel)
+    if gap is not None:
+        o.accelerate = 1
+        o.homo, o.lumo = float(gap[0]), float(gap[1])
     return o
 
 
@@ -220,6 +229,8 @@ def info_dict(info: Info) -> dict:
         "iderr": [float(info.iderr[i]) for i in range(m)],
         "ns": [float(info.ns[i]) for i in range(m)],
         "nx": [float(info.nx[i]) for i in range(m)],
+        "accelerated": int(info.accelerated),
+        "sigma_c": [float(info.sigma_c[i]) for i in range(m)],
     }
 
 
@@ -242,8 +253,11 @@ def timing_dict(t: Timing) -> dict:
 
 def density(h, n_occ: int, tol: float = 0.0, precision="fp16x2", max_layers=100, eps=0.0, bounds=None,
             refine=True, scale_log2=-1, want_energy=False, tile=0, kernel=0, out=None, workspace=None,
-            sync=True, stream=None, timed=False):
+            sync=True, stream=None, timed=False, gap=None):
     """D = theta(mu I - H) with Tr D = n_occ (Alg. 1) for a symmetric FP64 CUDA tensor H.
+
+    gap=(homo, lumo): accelerated layers (Sec. Accelerated Deep-NN SP2) from an interval
+    that lies inside the HOMO-LUMO gap of H.
 
     Returns (D, info) with info a dict (sync=True) or None (sync=False, nothing is
     read back; use `query`).  Argument errors raise SP2Error; numerical outcomes are
@@ -256,7 +270,7 @@ def density(h, n_occ: int, tol: float = 0.0, precision="fp16x2", max_layers=100,
     n = h.shape[0]
     if h.shape[1] != n or h.stride(1) != 1:
         raise ValueError("H must be square with unit column stride")
-    opts = options(precision, max_layers, eps, bounds, refine, scale_log2, want_energy, tile, kernel)
+    opts = options(precision, max_layers, eps, bounds, refine, scale_log2, want_energy, tile, kernel, gap)
     need = workspace_size(n, opts)
     if need == 0:
         raise SP2Error(SP2_EINVAL, "sp2_workspace_size")

@@ -44,14 +44,16 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stddef.h>\n#include <stdio.h>\n#include "sp2.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(sp2_options), sizeof(sp2_info),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(sp2_options), sizeof(sp2_info),"
         " offsetof(sp2_options, tile), offsetof(sp2_info, sigma), offsetof(sp2_info, iderr),"
-        " offsetof(sp2_info, nx));return 0;}\n")
+        " offsetof(sp2_info, nx), offsetof(sp2_options, homo), offsetof(sp2_info, accelerated),"
+        " offsetof(sp2_info, sigma_c));return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [ctypes.sizeof(sp2.Options), ctypes.sizeof(sp2.Info), sp2.Options.tile.offset,
-            sp2.Info.sigma.offset, sp2.Info.iderr.offset, sp2.Info.nx.offset]
+            sp2.Info.sigma.offset, sp2.Info.iderr.offset, sp2.Info.nx.offset, sp2.Options.homo.offset,
+            sp2.Info.accelerated.offset, sp2.Info.sigma_c.offset]
     assert got == want
 
 
@@ -60,6 +62,7 @@ def test_defaults_and_strings():
     sp2.lib().sp2_default_options(ctypes.byref(o))
     assert o.precision == sp2.FP16X2 and o.max_layers == 100 and o.refine == 1 and o.scale_log2 == -1
     assert o.eps == 0.0 and o.have_bounds == 0 and o.tile == 0
+    assert o.accelerate == 0 and o.homo == 0.0 and o.lumo == 0.0
     for st in range(-6, 1):
         assert isinstance(sp2.strerror(st), str) and sp2.strerror(st)
     assert "gfx950" in sp2.version()
@@ -90,6 +93,11 @@ def test_invalid_options_give_zero_workspace():
     assert sp2.workspace_size(100, sp2.options(kernel=7, tile=128)) > 0
     assert sp2.workspace_size(100, sp2.options(precision="fp64", kernel=6)) == 0
     assert sp2.workspace_size(100, sp2.options(precision="fp64", kernel=3)) > 0
+    # accelerated layers need homo < lumo, both finite
+    assert sp2.workspace_size(100, sp2.options(gap=(-1.0, 1.0))) > 0
+    assert sp2.workspace_size(100, sp2.options(gap=(1.0, -1.0))) == 0
+    assert sp2.workspace_size(100, sp2.options(gap=(0.5, 0.5))) == 0
+    assert sp2.workspace_size(100, sp2.options(gap=(float("nan"), 1.0))) == 0
 
 
 def test_argument_errors_return_before_device_work():
@@ -142,6 +150,7 @@ def test_batched_workspace_and_argument_errors():
     assert sp2.batched_workspace_size([0, 10], o) == 0
     assert sp2.batched_workspace_size(sizes, sp2.options(precision="fp64")) == 0
     assert sp2.batched_workspace_size(sizes, sp2.options(bounds=(-1.0, 1.0))) == 0
+    assert sp2.batched_workspace_size(sizes, sp2.options(gap=(-1.0, 1.0))) == 0
     fake = ctypes.c_void_p(256)
     P = ctypes.c_void_p * 1
     I = ctypes.c_int * 1
