@@ -84,7 +84,7 @@ def kernel_sources_digest():
     hsh = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2101_06385_amd", "csrc")
     for f in sorted(glob.glob(os.path.join(csrc, "k_square*")) + glob.glob(os.path.join(csrc, "k_sk_*")) +
-                    [os.path.join(csrc, "sp2_internal.h")]):
+                    [os.path.join(csrc, "sp2_args.h")]):
         hsh.update(os.path.basename(f).encode())
         hsh.update(open(f, "rb").read())
     return hsh.hexdigest()
@@ -119,9 +119,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-accel", action="store_true", help="skip the accelerated Deep-NN SP2 leg")
     ap.add_argument("--gen-device", default="cuda", help="where the QR of the workload generator runs")
-    ap.add_argument("--workload", default="density", choices=["density", "batched", "net"],
+    ap.add_argument("--workload", default="density", choices=["density", "batched", "net", "fermi"],
                     help="density: the N=8192 headline (default); batched: 64 Hamiltonians of uneven "
-                         "sizes in one graph; net: the 20-layer differentiable network at N=2048")
+                         "sizes in one graph; net: the 20-layer differentiable network at N=2048; fermi: "
+                         "the 11-layer optimized finite-temperature expansion at N (default 8192)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the path runs on one MI355X); "
@@ -131,6 +132,8 @@ def main():
         return bench_batched(args)
     if args.workload == "net":
         return bench_net(args)
+    if args.workload == "fermi":
+        return bench_fermi(args)
 
     import numpy as np
     import torch
@@ -480,6 +483,70 @@ def bench_net(args):
                      "frac": round(f_fwd / (np.mean(fwd) * 1e-3) / 1e12 / PEAK_FP16_TFLOPS, 4), "traffic": None,
                      "kernel": "forward layers (split squaring kernel); the adjoint runs on the FP32 peak 157.3"},
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_fermi(args):
+    """The optimized finite-temperature expansion of the paper's example (11 layers, beta = 40
+    and mu = 1/2 in the rescaled energy) fitted on the host and applied to an N x N
+    Hamiltonian (spectrum U[-15,15] eV, Gershgorin bounds): one step = sp2_fermi_apply."""
+    import numpy as np
+    import torch
+
+    from paper_2101_06385_amd import sp2, workloads
+
+    dev = torch.device("cuda:0")
+    n, L = args.n, 11
+    rng = np.random.default_rng(7000 + n)
+    eps = np.sort(rng.uniform(-15.0, 15.0, n))
+    gen = None if args.gen_device == "cpu" else "cuda:0"
+    q = workloads.haar_orthogonal(rng, n, gen)
+    h = torch.from_numpy(workloads.symmetric_from_eigen(q, eps, gen)).to(dev)
+    bounds = sp2.spectral_bounds(h)
+    span = bounds[1] - bounds[0]
+    t0 = time.perf_counter()
+    theta, c, loss = sp2.fermi_fit(L, bounds[0] + 0.5 * span, span / 40.0, bounds)
+    fit_ms = (time.perf_counter() - t0) * 1e3
+    out_d = torch.empty_like(h)
+    ws = sp2.alloc_workspace(sp2.fermi_workspace_size(n, bounds, args.precision), dev)
+    for _ in range(args.warmup):
+        sp2.fermi_apply(h, theta, c, bounds, precision=args.precision, out=out_d, workspace=ws, observables=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        sp2.fermi_apply(h, theta, c, bounds, precision=args.precision, out=out_d, workspace=ws, observables=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) * 1e3 / args.steps
+    split = args.precision in ("fp16x2", "bf16x2")
+    flop = L * (flop_split_layer(n) if split else flop_plain_layer(n))
+    value = flop / (ms * 1e-3) / 1e12
+    _, obs = sp2.fermi_apply(h, theta, c, bounds, precision=args.precision, out=out_d, workspace=ws)
+    log("fermi: %d layers at N=%d, %.2f ms per call, %.1f TFLOP/s; fit %.0f ms on the host, loss %.2e"
+        % (L, n, ms, value, fit_ms, loss))
+    out = {
+        "metric": "optimized finite-temperature SP2 expansion TFLOP/s (N=%d, 11 layers, beta=40)" % n,
+        "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16" if args.precision == "fp16x2" else args.precision, "data": "synthetic",
+        "config": {"workload": "Fermi operator N=%d, spectrum U[-15,15] eV, Gershgorin bounds, 11 layers fitted "
+                               "for beta=40, mu=1/2 in the rescaled energy" % n, "precision": args.precision},
+        "fit_ms_host": round(fit_ms, 1), "fit_loss": loss, "trace": obs[0],
+    }
+    if not args.no_cpu_baseline:
+        from oracle import fermi as ofermi
+
+        x = (eps - bounds[0]) / span
+        vals = ofermi.model_scalar(x, theta, c)
+        rows = [0, n // 2, n - 1]
+        ref = (q[rows] * vals[None, :]) @ q.T
+        d_rows = out_d[rows].cpu().numpy()
+        fd = ofermi.fermi(x, 40.0, 0.5)
+        exact = (q[rows] * fd[None, :]) @ q.T
+        out["accuracy"] = {"max_err_vs_network_rows": float(np.abs(d_rows - ref).max()),
+                           "max_err_vs_fermi_rows": float(np.abs(d_rows - exact).max()),
+                           "trace_vs_network": float(obs[0] - vals.sum()),
+                           "fit_max_err_on_spectrum": float(np.abs(vals - fd).max())}
+        log("fermi accuracy: %s" % out["accuracy"])
     print(json.dumps(out), flush=True)
 
 

@@ -295,6 +295,49 @@ int sp2_net_backward(const float* dGK, int ldg, int n, int K, const float* dW, c
                      float* ddW, float* ddB, float* ddC, void* dWork, size_t work_bytes,
                      void* stream);
 
+/*
+ * Optimized finite-temperature expansion (Sec. "Optimized SP2 Finite Temperature
+ * Fermi-Operator Expansion"): L layers of Eq. general SP2 on the rescaled spectrum
+ * x in [0, 1] of H,
+ *     x_0 = x,  x_k = theta[3(k-1)] x_{k-1}^2 + theta[3(k-1)+1] x_{k-1} + theta[3(k-1)+2],
+ * read out as F~(x) = 1 - sum_{i=0}^{L} c[i] x_i, fitted to the Fermi function
+ * F = 1/(exp((e - mu)/kT) + 1) of Eq. fermi.
+ *
+ * sp2_fermi_fit (host only) fits theta (3 L doubles) and c (L + 1 doubles, host) by
+ * Levenberg-Marquardt to F on `grid` equally spaced points of [0, 1] with trapezoid
+ * weights, where x = (e - emin)/(emax - emin): mu and kT are in energy units and [emin,
+ * emax] are the spectral bounds that sp2_fermi_apply will use.  Marquardt damping
+ * (lambda from 1e-3, /10 on an accepted step, x10 otherwise), at most max_iter steps.
+ * The start is the truncated SP2 expansion (x^2 or 2x - x^2 per layer, whichever keeps the
+ * image of the rescaled mu closest to 1/2; read-out 1 - x_L).  *loss (may be NULL)
+ * receives the weighted sum of squares.  1 <= layers <= 127, 3 <= grid <= 1e6,
+ * kT > 0, emax > emin, or SP2_EINVAL.
+ *
+ * sp2_fermi_apply evaluates the fitted network on the matrix: X_0 = (H - emin I)/(emax -
+ * emin) with opt->emin/emax (opt->have_bounds must be set: they are the bounds used in the
+ * fit), X_{k+1} = theta_k,1 X_k^2 + theta_k,2 X_k + theta_k,3 I in opt->precision (the layer
+ * kernels of sp2_density; split modes with FP32 state), and D = I - sum_i c_i X_i
+ * accumulated in FP64, written n x n FP64 (leading dimension ldd, symmetric).  theta and c
+ * are host arrays; dH, dD device.  Enqueued on `stream`; if obs (host, 3 doubles) is
+ * non-NULL the call synchronizes and writes Tr D, ||D||_F^2 and Tr[D H] there.  dWork
+ * (256-byte aligned) holds sp2_fermi_workspace_size(n, opt) bytes.  Errors: SP2_EINVAL
+ * (arguments, non-finite coefficients, no bounds, accelerate set), SP2_ENOMEM,
+ * SP2_EDEVICE, SP2_ENONFINITE (non-finite observables).
+ *
+ * sp2_spectral_bounds computes the FP64 Gershgorin bounds of Alg. 1's default (row
+ * intervals widened outward by the summation error bound) on the device and returns them
+ * to the host (synchronizes); workspace sp2_spectral_bounds_workspace_size(n) bytes.
+ */
+int sp2_fermi_fit(int layers, double mu, double kT, double emin, double emax, int grid, int max_iter,
+                  double* theta, double* c, double* loss);
+size_t sp2_fermi_workspace_size(int n, const sp2_options* opt);
+int sp2_fermi_apply(const double* dH, int ldh, double* dD, int ldd, int n, int layers, const double* theta,
+                    const double* c, const sp2_options* opt, double* obs, void* dWork, size_t work_bytes,
+                    void* stream);
+size_t sp2_spectral_bounds_workspace_size(int n);
+int sp2_spectral_bounds(const double* dH, int ldh, int n, double* emin, double* emax, void* dWork,
+                        size_t work_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

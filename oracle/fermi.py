@@ -93,8 +93,10 @@ def residuals(p, layers: int, x, w, target):
 
 
 def loss(p, layers: int, x, w, target) -> float:
-    r = residuals(p, layers, x, w, target)
-    return float(r @ r)
+    """Weighted sum of squares; inf or nan for a trial step that overflows (then rejected)."""
+    with np.errstate(over="ignore", invalid="ignore"):
+        r = residuals(p, layers, x, w, target)
+        return float(r @ r)
 
 
 def jacobian(p, layers: int, x, w):

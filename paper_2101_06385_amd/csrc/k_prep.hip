@@ -537,6 +537,69 @@ __global__ void k_zero_ints(int* p, int count) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
+// Finite-temperature read-out D = (1 - c_0) I + c_0 S_0 - sum_{k>=1} c_k X_k accumulated in
+// FP64 over the padded matrix: first = 1 sets acc = a X + diag I, otherwise acc += a X.
+// Two elements per thread and iteration (n_p is a multiple of 64).
+template <typename St>
+__global__ __launch_bounds__(kThreads) void k_readout(double* __restrict__ acc, const St* __restrict__ x, int np,
+                                                      double a, double diag, int first) {
+    const size_t total = (size_t)np * np / 2;
+    for (size_t q = (size_t)blockIdx.x * kThreads + threadIdx.x; q < total; q += (size_t)gridDim.x * kThreads) {
+        const size_t idx = 2 * q;
+        const int i = (int)(idx / np), j = (int)(idx % np);
+        double v0 = a * (double)x[idx], v1 = a * (double)x[idx + 1];
+        if (first) {
+            if (i == j) v0 += diag;
+            if (i == j + 1) v1 += diag;
+            acc[idx] = v0;
+            acc[idx + 1] = v1;
+        } else {
+            acc[idx] += v0;
+            acc[idx + 1] += v1;
+        }
+    }
+}
+
+// n x n leading block of the padded accumulator into D (leading dimension ldd)
+__global__ __launch_bounds__(kThreads) void k_copy_out(const double* __restrict__ acc, int np,
+                                                       double* __restrict__ d, int ldd, int n) {
+    const size_t total = (size_t)n * n;
+    for (size_t idx = (size_t)blockIdx.x * kThreads + threadIdx.x; idx < total; idx += (size_t)gridDim.x * kThreads) {
+        const int i = (int)(idx / n), j = (int)(idx % n);
+        d[(size_t)i * ldd + j] = acc[(size_t)i * np + j];
+    }
+}
+
+// Up to kMaxCoefs floats passed by value into device memory (kernel arguments are part of
+// the launch, so this works inside a captured stream as well).
+constexpr int kMaxCoefs = 3 * SP2_MAX_LAYERS;
+template <typename T>
+struct CoefBlock {
+    T v[kMaxCoefs];
+};
+template <typename T>
+__global__ void k_store_coefs(T* __restrict__ dst, CoefBlock<T> b, int count) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = b.v[i];
+}
+
+// Fixed-order sum of per-block triples (Tr part, ||.||_F^2 part, Tr[DH] part).
+__global__ __launch_bounds__(kThreads) void k_sum3(const double* __restrict__ parts, int nparts,
+                                                   double* __restrict__ out3) {
+    __shared__ double sh[3 * kThreads];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < nparts; i += kThreads) {
+        v[0] += parts[3 * i];
+        v[1] += parts[3 * i + 1];
+        v[2] += parts[3 * i + 2];
+    }
+    block_sum<3>(v, sh);
+    if (threadIdx.x == 0) {
+        out3[0] = v[0];
+        out3[1] = v[1];
+        out3[2] = v[2];
+    }
+}
+
 // Occupation 0 or n: no recursion is run; the state records a converged call of 0 layers.
 __global__ void k_mark_trivial(DevState* st) {
     if (threadIdx.x == 0) {
@@ -766,6 +829,43 @@ hipError_t launch_sum_parts(const double* parts, int nparts, double* out2, hipSt
 namespace sp2 {
 hipError_t launch_set3(float* dst, float a, float b, float c, hipStream_t s) {
     hipLaunchKernelGGL(k_set3, dim3(1), dim3(64), 0, s, dst, a, b, c);
+    return hipGetLastError();
+}
+hipError_t launch_readout(int precision, double* acc, const void* x, int np, double a, double diag, int first,
+                          hipStream_t s) {
+    const size_t pairs = (size_t)np * np / 2;
+    size_t g = (pairs + kThreads - 1) / kThreads;
+    if (g > 4096) g = 4096;
+    if (precision == SP2_FP64)
+        hipLaunchKernelGGL(k_readout<double>, dim3((unsigned)g), dim3(kThreads), 0, s, acc, (const double*)x, np, a,
+                           diag, first);
+    else
+        hipLaunchKernelGGL(k_readout<float>, dim3((unsigned)g), dim3(kThreads), 0, s, acc, (const float*)x, np, a,
+                           diag, first);
+    return hipGetLastError();
+}
+hipError_t launch_copy_out(const double* acc, int np, double* d, int ldd, int n, hipStream_t s) {
+    size_t g = ((size_t)n * n + kThreads - 1) / kThreads;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_copy_out, dim3((unsigned)g), dim3(kThreads), 0, s, acc, np, d, ldd, n);
+    return hipGetLastError();
+}
+hipError_t launch_store_coefs(float* dst, const double* vals, int count, hipStream_t s) {
+    if (count < 0 || count > kMaxCoefs) return hipErrorInvalidValue;
+    CoefBlock<float> b;
+    for (int i = 0; i < kMaxCoefs; ++i) b.v[i] = i < count ? (float)vals[i] : 0.f;
+    hipLaunchKernelGGL(k_store_coefs<float>, dim3(1), dim3(128), 0, s, dst, b, count);
+    return hipGetLastError();
+}
+hipError_t launch_store_coefs64(double* dst, const double* vals, int count, hipStream_t s) {
+    if (count < 0 || count > kMaxCoefs) return hipErrorInvalidValue;
+    CoefBlock<double> b;
+    for (int i = 0; i < kMaxCoefs; ++i) b.v[i] = i < count ? vals[i] : 0.0;
+    hipLaunchKernelGGL(k_store_coefs<double>, dim3(1), dim3(128), 0, s, dst, b, count);
+    return hipGetLastError();
+}
+hipError_t launch_sum3(const double* parts, int nparts, double* out3, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum3, dim3(1), dim3(kThreads), 0, s, parts, nparts, out3);
     return hipGetLastError();
 }
 hipError_t launch_zero_ints(int* p, int count, hipStream_t s) {

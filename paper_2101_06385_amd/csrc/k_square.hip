@@ -418,7 +418,9 @@ __device__ __forceinline__ void plain_body(const SquareArgs& a, int t) {
     }
 
     // ---------------------------------------------------------------- epilogue
-    const E alpha = (E)a.coef[0], beta = (E)a.coef[1], gamma = (E)a.coef[2];
+    const E alpha = a.coef64 ? (E)a.coef64[0] : (E)a.coef[0];
+    const E beta = a.coef64 ? (E)a.coef64[1] : (E)a.coef[1];
+    const E gamma = a.coef64 ? (E)a.coef64[2] : (E)a.coef[2];
     E* so = (E*)a.s_out;
     const E* si = (const E*)a.s_in;
     const int ldo = a.ld_out, nv = a.n_valid;

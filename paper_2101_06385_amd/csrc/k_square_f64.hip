@@ -214,7 +214,9 @@ __device__ __forceinline__ void f64_body(const SquareArgs& a, int t, int kb, int
     }
 
     // ------------------------------------------------------------------- epilogue
-    const double alpha = (double)a.coef[0], beta = (double)a.coef[1], gamma = (double)a.coef[2];
+    const double alpha = a.coef64 ? a.coef64[0] : (double)a.coef[0];
+    const double beta = a.coef64 ? a.coef64[1] : (double)a.coef[1];
+    const double gamma = a.coef64 ? a.coef64[2] : (double)a.coef[2];
     double* so = (double*)a.s_out;
     const double* si = (const double*)a.s_in;
     const int ldo = a.ld_out, nv = a.n_valid;

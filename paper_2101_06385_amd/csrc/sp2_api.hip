@@ -602,6 +602,160 @@ int sp2_query(const void* dWork, int n, const sp2_options* opt, sp2_info* info, 
     return host.status;
 }
 
+// ----------------------------------------------------------------------------------
+// Optimized finite-temperature expansion on matrices (Eq. general SP2 with its read-out)
+// ----------------------------------------------------------------------------------
+static bool fermi_plan(int n, const sp2_options* opt, Opts* o, Plan* p, size_t* off_coef, size_t* off_sum,
+                       size_t* total) {
+    if (n <= 0 || n > 65536 || !read_opts(opt, o)) return false;
+    if (!o->have_bounds || o->accelerate) return false;
+    o->refine = 1;   // the FP64 refinement buffer holds the read-out accumulator
+    make_plan(n, *o, p);
+    *off_coef = align_up(p->total);   // FP32 copy, then FP64 copy of the layer coefficients
+    *off_sum = align_up(*off_coef + (sizeof(float) + sizeof(double)) * 3 * SP2_MAX_LAYERS);
+    *total = align_up(*off_sum + sizeof(double) * 3);
+    return true;
+}
+
+size_t sp2_fermi_workspace_size(int n, const sp2_options* opt) {
+    Opts o;
+    Plan p;
+    size_t oc, os, total;
+    return fermi_plan(n, opt, &o, &p, &oc, &os, &total) ? total : 0;
+}
+
+int sp2_fermi_apply(const double* dH, int ldh, double* dD, int ldd, int n, int layers, const double* theta,
+                    const double* c, const sp2_options* opt, double* obs, void* dWork, size_t work_bytes,
+                    void* stream) {
+    Opts o;
+    Plan p;
+    size_t off_coef, off_sum, total;
+    if (!fermi_plan(n, opt, &o, &p, &off_coef, &off_sum, &total)) return SP2_EINVAL;
+    if (ldh < n || ldd < n || !dH || !dD || !dWork || !theta || !c) return SP2_EINVAL;
+    if (layers < 1 || layers >= SP2_MAX_LAYERS || ((uintptr_t)dWork) % kAlign) return SP2_EINVAL;
+    for (int k = 0; k < 3 * layers; ++k)
+        if (!isfinite(theta[k])) return SP2_EINVAL;
+    for (int k = 0; k <= layers; ++k)
+        if (!isfinite(c[k])) return SP2_EINVAL;
+    if (work_bytes < total) return SP2_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)dWork;
+    DevState* st = (DevState*)ws;
+    // S_0 = (emax I - H)/(emax - emin) is what the input layer builds; the model's input is
+    // X_0 = I - S_0, so layer 0 is rewritten in S_0: t1 (1 - s)^2 + t2 (1 - s) + t3 =
+    // t1 s^2 + (-2 t1 - t2) s + (t1 + t2 + t3), and the read-out starts from
+    // I - c_0 X_0 = (1 - c_0) I + c_0 S_0.
+    double coef[3 * SP2_MAX_LAYERS];
+    for (int k = 0; k < layers; ++k) {
+        const double t1 = theta[3 * k], t2 = theta[3 * k + 1], t3 = theta[3 * k + 2];
+        coef[3 * k] = t1;
+        coef[3 * k + 1] = k == 0 ? -2.0 * t1 - t2 : t2;
+        coef[3 * k + 2] = k == 0 ? t1 + t2 + t3 : t3;
+    }
+    float* dcoef = (float*)(ws + off_coef);
+    double* dcoef64 = (double*)(ws + off_coef + align_up(sizeof(float) * 3 * SP2_MAX_LAYERS));
+    double* acc = (double*)(ws + p.off_s64);
+    DevState init = initial_state(n, 0, 0.0, o, p);
+    SP2_TRY(launch_state_init(st, init, s));
+    SP2_TRY(launch_store_coefs(dcoef, coef, 3 * layers, s));
+    SP2_TRY(launch_store_coefs64(dcoef64, coef, 3 * layers, s));
+    void* S[2] = {ws + p.off_s[0], ws + p.off_s[1]};
+    void* P[2][2] = {{p.split ? ws + p.off_p[0][0] : nullptr, p.split ? ws + p.off_p[0][1] : nullptr},
+                     {p.split ? ws + p.off_p[1][0] : nullptr, p.split ? ws + p.off_p[1][1] : nullptr}};
+    double* init_parts = (double*)(ws + p.off_init_parts);
+    SP2_TRY(launch_init_np(dH, ldh, st, p.np, o.precision, S[0], P[0][0], P[0][1], p.scale_log2, init_parts, s));
+    SP2_TRY(launch_readout(o.precision, acc, S[0], p.np, c[0], 1.0 - c[0], 1, s));
+    StreamK sk;
+    memset(&sk, 0, sizeof(sk));
+    int sk_variant = 0;
+    const bool use_sk = sk_resolve(p, &sk, &sk_variant);
+    if (use_sk) {
+        sk.partial = (float*)(ws + p.off_sk_partial);
+        sk.counter = (int*)(ws + p.off_sk_counter);
+        SP2_TRY(launch_zero_ints(sk.counter, kMaxSkGrid, s));
+    }
+    StreamK f64sk;
+    memset(&f64sk, 0, sizeof(f64sk));
+    if (p.f64_sk) {
+        f64sk = f64_sk_resolve(p.np, ws + p.off_f64_partial, (int*)(ws + p.off_f64_counter));
+        if (f64sk.grid > 0) SP2_TRY(launch_zero_ints(f64sk.counter, kMaxSkGrid, s));
+    }
+    SquareArgs a;
+    memset(&a, 0, sizeof(a));
+    a.parts = nullptr;
+    a.skip = nullptr;
+    a.np = p.np;
+    a.ld_out = p.np;
+    a.n_valid = p.np;
+    a.n_real = n;
+    a.T = p.main_T;
+    a.ntiles = p.main_tiles;
+    a.per = p.main_per;
+    a.out_scale = ldexpf(1.f, -2 * p.scale_log2);
+    a.in_scale = ldexpf(1.f, p.scale_log2);
+    for (int k = 0; k < layers; ++k) {
+        const int in = k & 1, out = in ^ 1;
+        a.coef = dcoef + 3 * k;
+        a.coef64 = o.precision == SP2_FP64 ? dcoef64 + 3 * k : nullptr;
+        a.x0 = p.split ? P[in][0] : S[in];
+        a.x1 = p.split ? P[in][1] : nullptr;
+        a.s_in = S[in];
+        a.s_out = S[out];
+        a.p0_out = P[out][0];
+        a.p1_out = P[out][1];
+        if (use_sk)
+            SP2_TRY(launch_square_sk(o.precision, p.tile_main, sk_variant, a, sk, s));
+        else if (p.split)
+            SP2_TRY(launch_split_tile_layer(o.precision, p.tile_main, p.kernel, a, s));
+        else if (o.precision == SP2_FP64)
+            SP2_TRY(launch_f64_layer(p.tile_main, o.kernel, a, &f64sk, s));
+        else
+            SP2_TRY(launch_square_plain(o.precision, p.tile_main, a, s));
+        SP2_TRY(launch_readout(o.precision, acc, S[out], p.np, -c[k + 1], 0.0, 0, s));
+    }
+    SP2_TRY(launch_copy_out(acc, p.np, dD, ldd, n, s));
+    if (!obs) return SP2_OK;
+    double* dstats = (double*)(ws + p.off_dstats);
+    double* sums = (double*)(ws + off_sum);
+    int nd = 0;
+    SP2_TRY(launch_dstats(dD, ldd, dH, ldh, n, dstats, &nd, s));
+    SP2_TRY(launch_sum3(dstats, nd, sums, s));
+    SP2_TRY(hipMemcpyAsync(obs, sums, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+    SP2_TRY(hipStreamSynchronize(s));
+    return (isfinite(obs[0]) && isfinite(obs[1])) ? SP2_OK : SP2_ENONFINITE;
+}
+
+size_t sp2_spectral_bounds_workspace_size(int n) {
+    if (n <= 0 || n > 65536) return 0;
+    return align_up(sizeof(DevState)) + align_up(sizeof(double) * 3 * gershgorin_blocks(n));
+}
+
+int sp2_spectral_bounds(const double* dH, int ldh, int n, double* emin, double* emax, void* dWork,
+                        size_t work_bytes, void* stream) {
+    if (n <= 0 || n > 65536 || ldh < n || !dH || !emin || !emax || !dWork) return SP2_EINVAL;
+    if (((uintptr_t)dWork) % kAlign) return SP2_EINVAL;
+    if (work_bytes < sp2_spectral_bounds_workspace_size(n)) return SP2_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)dWork;
+    DevState* st = (DevState*)ws;
+    double* gersh = (double*)(ws + align_up(sizeof(DevState)));
+    DevState init;
+    memset(&init, 0, sizeof(init));
+    init.n = n;
+    init.n_padded = n;
+    init.status = SP2_OK;
+    SP2_TRY(launch_state_init(st, init, s));
+    int nb = 0;
+    SP2_TRY(launch_gershgorin(dH, ldh, n, gersh, &nb, s));
+    SP2_TRY(launch_bounds(st, gersh, nb, s));
+    DevState host;
+    SP2_TRY(hipStreamSynchronize(s));
+    SP2_TRY(hipMemcpy(&host, st, sizeof(DevState), hipMemcpyDeviceToHost));
+    *emin = host.emin;
+    *emax = host.emax;
+    return host.status;
+}
+
 int sp2_square_padded(int n, int precision, int tile) {
     if (n <= 0) return 0;
     const bool split = precision == SP2_FP16X2 || precision == SP2_BF16X2;

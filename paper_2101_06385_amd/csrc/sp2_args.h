@@ -1,0 +1,47 @@
+// Arguments of the squaring kernels and of their persistent schedule (the parts of the
+// interface the kernel code depends on).
+#pragma once
+
+namespace sp2 {
+
+// ---------------------------------------------------------------------------------
+// Arguments of the squaring kernels: Y = alpha X^2 + beta X + gamma I, written to
+// both triangles (exactly symmetric), optionally split into half-precision planes, with
+// FP64 partial sums of Tr Y and ||Y||_F^2 per output tile.
+// ---------------------------------------------------------------------------------
+struct SquareArgs {
+    const void* x0;       // split modes: high plane of X (np x np, ld np); plain: X itself
+    const void* x1;       // split modes: low plane of X
+    const void* s_in;     // X in the state precision (beta term), ld = np
+    void* s_out;          // Y in the state precision, ld = ld_out
+    void* p0_out;         // split modes: planes of Y (ld np), or null
+    void* p1_out;
+    double* parts;        // 2 doubles per tile, or null
+    const float* coef;    // (alpha, beta, gamma)
+    const double* coef64; // FP64 layer kernels: (alpha, beta, gamma) in FP64 when non-null
+    const int* skip;      // null, or a flag that makes every workgroup return at once
+    int np;               // padded edge (multiple of the tile)
+    int ld_out;           // leading dimension of s_out
+    int n_valid;          // rows/cols >= n_valid of s_out are not written
+    int n_real;           // logical edge: the gamma I term stops here so the padding stays zero
+    int T;                // tiles per edge
+    int ntiles;           // T (T + 1) / 2
+    int per;              // ceil(ntiles / 8)
+    float out_scale;      // split modes: 2^-2s applied to the accumulated products
+    float in_scale;       // split modes: 2^s applied before splitting Y
+};
+
+// Schedule of the persistent split-square kernel: G workgroups run `rounds` whole rounds
+// of tiles, then the `tail_tiles` leftover tiles are each cut into `chunks` K-chunks.
+// `partial` holds one FP32 tile accumulator per tail chunk, `counter` one arrival count
+// per tail tile (zeroed at the start of every call; each executed layer adds `chunks`).
+constexpr int kMaxSkGrid = 1024;
+constexpr int kSkVariants = 6;
+struct StreamK {
+    int grid, rounds, tail_tiles, chunks;
+    float* partial;     // FP32 partial tiles (split squaring, adjoint)
+    int* counter;       // arrivals per tail tile, counted modulo chunks
+    double* fpartial;   // FP64 partial tiles (FP64 layer)
+};
+
+}  // namespace sp2

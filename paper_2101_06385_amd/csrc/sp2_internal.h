@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "../../include/sp2.h"
+#include "sp2_args.h"
 
 namespace sp2 {
 
@@ -96,38 +97,7 @@ __device__ inline int find_group(const int* offs, int n, int b) {
     return lo;
 }
 
-// ---------------------------------------------------------------------------------
-// Arguments of the squaring kernels: Y = alpha X^2 + beta X + gamma I, written to
-// both triangles (exactly symmetric), optionally split into half-precision planes, with
-// FP64 partial sums of Tr Y and ||Y||_F^2 per output tile.
-// ---------------------------------------------------------------------------------
-struct SquareArgs {
-    const void* x0;       // split modes: high plane of X (np x np, ld np); plain: X itself
-    const void* x1;       // split modes: low plane of X
-    const void* s_in;     // X in the state precision (beta term), ld = np
-    void* s_out;          // Y in the state precision, ld = ld_out
-    void* p0_out;         // split modes: planes of Y (ld np), or null
-    void* p1_out;
-    double* parts;        // 2 doubles per tile, or null
-    const float* coef;    // (alpha, beta, gamma)
-    const int* skip;      // null, or a flag that makes every workgroup return at once
-    int np;               // padded edge (multiple of the tile)
-    int ld_out;           // leading dimension of s_out
-    int n_valid;          // rows/cols >= n_valid of s_out are not written
-    int n_real;           // logical edge: the gamma I term stops here so the padding stays zero
-    int T;                // tiles per edge
-    int ntiles;           // T (T + 1) / 2
-    int per;              // ceil(ntiles / 8)
-    float out_scale;      // split modes: 2^-2s applied to the accumulated products
-    float in_scale;       // split modes: 2^s applied before splitting Y
-};
 
-// Schedule of the persistent split-square kernel: G workgroups run `rounds` whole rounds
-// of tiles, then the `tail_tiles` leftover tiles are each cut into `chunks` K-chunks.
-// `partial` holds one FP32 tile accumulator per tail chunk, `counter` one arrival count
-// per tail tile (zeroed at the start of every call; each executed layer adds `chunks`).
-constexpr int kMaxSkGrid = 1024;
-constexpr int kSkVariants = 6;
 
 // Autotuner table (sp2_tune.hip): the fastest measured schedule per (device, kind,
 // precision, key); kind single: key = n rounded up to 256; kind batched: key = hash of the
@@ -137,12 +107,6 @@ unsigned long long tune_key_single(int n);
 unsigned long long tune_key_batched(int batch, const int* n);
 bool tune_lookup(int kind, int precision, unsigned long long key, int* tile, int* kernel);
 void tune_store(int kind, int precision, unsigned long long key, int tile, int kernel, float ms);
-struct StreamK {
-    int grid, rounds, tail_tiles, chunks;
-    float* partial;     // FP32 partial tiles (split squaring, adjoint)
-    int* counter;       // arrivals per tail tile, counted modulo chunks
-    double* fpartial;   // FP64 partial tiles (FP64 layer)
-};
 
 // Arguments of the FP32 adjoint layer of the generalized-SP2 network.
 struct AdjointArgs {
@@ -241,6 +205,13 @@ hipError_t launch_split(const float* x, void* p0, void* p1, int np, int precisio
                         hipStream_t s);
 hipError_t launch_sum_parts(const double* parts, int nparts, double* out2, hipStream_t s);
 hipError_t launch_set3(float* dst, float a, float b, float c, hipStream_t s);
+// finite-temperature read-out: acc (FP64, n_p x n_p) = a X + diag I (first) or += a X
+hipError_t launch_readout(int precision, double* acc, const void* x, int np, double a, double diag, int first,
+                          hipStream_t s);
+hipError_t launch_copy_out(const double* acc, int np, double* d, int ldd, int n, hipStream_t s);
+hipError_t launch_store_coefs(float* dst, const double* vals, int count, hipStream_t s);   // rounded to FP32
+hipError_t launch_store_coefs64(double* dst, const double* vals, int count, hipStream_t s);
+hipError_t launch_sum3(const double* parts, int nparts, double* out3, hipStream_t s);
 hipError_t launch_mark_trivial(DevState* st, hipStream_t s);
 
 }  // namespace sp2

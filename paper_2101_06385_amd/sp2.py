@@ -146,6 +146,18 @@ def lib() -> ctypes.CDLL:
     L.sp2_net_backward.argtypes = [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_int, c_int,
                                    c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
     L.sp2_net_backward.restype = c_int
+    pd = ctypes.POINTER(c_double)
+    L.sp2_fermi_fit.argtypes = [c_int, c_double, c_double, c_double, c_double, c_int, c_int, pd, pd, pd]
+    L.sp2_fermi_fit.restype = c_int
+    L.sp2_fermi_workspace_size.argtypes = [c_int, ctypes.POINTER(Options)]
+    L.sp2_fermi_workspace_size.restype = c_size_t
+    L.sp2_fermi_apply.argtypes = [c_void_p, c_int, c_void_p, c_int, c_int, c_int, pd, pd, ctypes.POINTER(Options), pd,
+                                  c_void_p, c_size_t, c_void_p]
+    L.sp2_fermi_apply.restype = c_int
+    L.sp2_spectral_bounds_workspace_size.argtypes = [c_int]
+    L.sp2_spectral_bounds_workspace_size.restype = c_size_t
+    L.sp2_spectral_bounds.argtypes = [c_void_p, c_int, c_int, pd, pd, c_void_p, c_size_t, c_void_p]
+    L.sp2_spectral_bounds.restype = c_int
     _lib = L
     return L
 
@@ -472,3 +484,72 @@ def net_backward(gk, w, b, c, workspace, precision="fp16x2", ckpt_every=0, want_
     if st != SP2_OK:
         raise SP2Error(st, "sp2_net_backward")
     return dw, db, dc, g0
+
+
+# ------------------------------------------------------------------ finite-temperature expansion
+def fermi_fit(layers: int, mu: float, kT: float, bounds, grid: int = 1001, max_iter: int = 300):
+    """Fit the L-layer expansion (Eq. general SP2 + read-out) to the Fermi function at (mu, kT)
+    for spectral bounds `bounds` = (emin, emax) (see sp2_fermi_fit).  Returns (theta (L, 3),
+    c (L + 1,), loss) as NumPy arrays / float."""
+    import numpy as np
+
+    theta = (ctypes.c_double * (3 * layers))()
+    c = (ctypes.c_double * (layers + 1))()
+    loss = ctypes.c_double()
+    st = lib().sp2_fermi_fit(int(layers), float(mu), float(kT), float(bounds[0]), float(bounds[1]), int(grid),
+                             int(max_iter), theta, c, ctypes.byref(loss))
+    if st != SP2_OK:
+        raise SP2Error(st, "sp2_fermi_fit")
+    return np.array(theta[:]).reshape(layers, 3), np.array(c[:]), float(loss.value)
+
+
+def spectral_bounds(h, stream=None):
+    """FP64 Gershgorin bounds of a symmetric FP64 CUDA tensor, computed on the device."""
+    n = h.shape[0]
+    ws = alloc_workspace(lib().sp2_spectral_bounds_workspace_size(n), h.device)
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    st = lib().sp2_spectral_bounds(ctypes.c_void_p(h.data_ptr()), h.stride(0), n, ctypes.byref(lo), ctypes.byref(hi),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(h.device, stream))
+    if st != SP2_OK:
+        raise SP2Error(st, "sp2_spectral_bounds")
+    return float(lo.value), float(hi.value)
+
+
+def fermi_workspace_size(n: int, bounds, precision="fp16x2", tile=0, kernel=0) -> int:
+    o = options(precision, bounds=bounds, tile=tile, kernel=kernel)
+    return int(lib().sp2_fermi_workspace_size(int(n), ctypes.byref(o)))
+
+
+def fermi_apply(h, theta, c, bounds, precision="fp16x2", tile=0, kernel=0, out=None, workspace=None, stream=None,
+                observables=True):
+    """D = I - sum_i c_i X_i for the fitted network on the matrix H (see sp2_fermi_apply).
+    Returns (D, (Tr D, ||D||_F^2, Tr[D H]) or None)."""
+    import numpy as np
+    import torch
+
+    if not (isinstance(h, torch.Tensor) and h.is_cuda and h.dtype == torch.float64 and h.dim() == 2
+            and h.shape[0] == h.shape[1] and h.stride(1) == 1):
+        raise TypeError("H must be a square 2-D float64 CUDA tensor with unit column stride")
+    theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).ravel())
+    c = np.ascontiguousarray(np.asarray(c, dtype=np.float64).ravel())
+    layers = theta.size // 3
+    if theta.size != 3 * layers or c.size != layers + 1:
+        raise ValueError("theta must hold 3 L values and c L + 1")
+    n = h.shape[0]
+    o = options(precision, bounds=bounds, tile=tile, kernel=kernel)
+    need = int(lib().sp2_fermi_workspace_size(n, ctypes.byref(o)))
+    if need == 0:
+        raise SP2Error(SP2_EINVAL, "sp2_fermi_workspace_size")
+    if workspace is None or workspace.numel() < need:
+        workspace = alloc_workspace(need, h.device)
+    if out is None:
+        out = torch.empty((n, n), dtype=torch.float64, device=h.device)
+    pd = ctypes.POINTER(ctypes.c_double)
+    obs = (ctypes.c_double * 3)() if observables else None
+    st = lib().sp2_fermi_apply(ctypes.c_void_p(h.data_ptr()), h.stride(0), ctypes.c_void_p(out.data_ptr()),
+                               out.stride(0), n, layers, theta.ctypes.data_as(pd), c.ctypes.data_as(pd),
+                               ctypes.byref(o), obs, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                               _stream_ptr(h.device, stream))
+    if st != SP2_OK:
+        raise SP2Error(st, "sp2_fermi_apply")
+    return out, (tuple(obs[:]) if obs is not None else None)
