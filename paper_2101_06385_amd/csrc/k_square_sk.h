@@ -472,6 +472,16 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
             const float osc = a.out_scale, isc = a.in_scale;
             const bool diag = (I == J);
             double tr = 0.0, fr = 0.0;
+            // Off-diagonal tiles: each 32 x 32 block goes transposed through this wave's LDS
+            // region (FP32 values, then both half planes) and is written to the mirror
+            // position as whole row segments (128 bytes of FP32, 64 bytes per plane) instead
+            // of one 16- or 8-byte piece per lane in 64 different rows.
+            constexpr int TF = 36, TH = 40;    // padded row pitches (floats, halves): 16-byte aligned rows
+            constexpr int WREG = 32 * TF * 4 + 2 * 32 * TH * 2;
+            static_assert(C::NW * WREG <= C::LDS, "mirror staging fits in the pipeline stages");
+            float* tf = (float*)(lds + owave * WREG);
+            T16* th0 = (T16*)(lds + owave * WREG + 32 * TF * 4);
+            T16* th1 = th0 + 32 * TH;
             static_for<0, MB>([&](auto m) {
                 static_for<0, NB>([&](auto n) {
                     const int col = J * BT + own * C::WTN + n * 32 + (olane & 31);
@@ -502,13 +512,14 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
                                 }
                                 fr += 2.0 * (double)y4[e] * (double)y4[e];
                             }
-                            const size_t moff = (size_t)col * np + row0;
-                            *(float4*)(so + moff) = make_float4(y4[0], y4[1], y4[2], y4[3]);
+                            // transposed into LDS: row (olane & 31) holds this block's column
+                            const int lo = (olane & 31), ro = 8 * g + 4 * (olane >> 5);
+                            *(float4*)(tf + lo * TF + ro) = make_float4(y4[0], y4[1], y4[2], y4[3]);
                             if (p0) {
                                 vec4 q0 = {h0[0], h0[1], h0[2], h0[3]};
                                 vec4 q1 = {h1[0], h1[1], h1[2], h1[3]};
-                                *(vec4*)(p0 + moff) = q0;
-                                *(vec4*)(p1 + moff) = q1;
+                                *(vec4*)(th0 + lo * TH + ro) = q0;
+                                *(vec4*)(th1 + lo * TH + ro) = q1;
                             }
                         } else {
 #pragma unroll
@@ -536,6 +547,25 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
                             }
                         }
                     });
+                    if (!diag) {
+                        // mirror rows: block columns J*BT + own*WTN + n*32 + c, entries at block rows
+                        __syncthreads();
+                        const size_t mrow0 = (size_t)(J * BT + own * C::WTN + n * 32);
+                        const int mcol0 = I * BT + owm * C::WTM + m * 32;
+                        static_for<0, 4>([&](auto k) {
+                            const int c = 8 * k + (olane >> 3), q = olane & 7;
+                            *(float4*)(so + (mrow0 + c) * np + mcol0 + 4 * q) = *(const float4*)(tf + c * TF + 4 * q);
+                        });
+                        if (p0) {
+                            static_for<0, 2>([&](auto k) {
+                                const int c = 16 * k + (olane >> 2), q = olane & 3;
+                                const size_t goff = (mrow0 + c) * np + mcol0 + 8 * q;
+                                *(vec8*)(p0 + goff) = *(const vec8*)(th0 + c * TH + 8 * q);
+                                *(vec8*)(p1 + goff) = *(const vec8*)(th1 + c * TH + 8 * q);
+                            });
+                        }
+                        __syncthreads();
+                    }
                 });
             });
             if (a.parts) {
