@@ -118,6 +118,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-accel", action="store_true", help="skip the accelerated Deep-NN SP2 leg")
+    ap.add_argument("--no-autotune", action="store_true", help="skip reporting the autotuner's choice")
     ap.add_argument("--gen-device", default="cuda", help="where the QR of the workload generator runs")
     ap.add_argument("--workload", default="density", choices=["density", "batched", "net", "fermi"],
                     help="density: the N=8192 headline (default); batched: 64 Hamiltonians of uneven "
@@ -321,6 +322,18 @@ def main():
             if "fp64" in out["accelerated"]:
                 out["accelerated"]["fp64"]["fro_error"] = float(np.linalg.norm(d64a.cpu().numpy() - d_ref))
         log("accuracy: %s" % acc)
+    props = torch.cuda.get_device_properties(dev)
+    out["env"] = {"device": props.name, "gcn_arch": getattr(props, "gcnArchName", ""),
+                  "compute_units": props.multi_processor_count, "hip": torch.version.hip}
+    if not args.no_autotune:
+        # the autotuner's choice at this size (after every timed leg; its table is reset so
+        # that nothing above depended on it)
+        tuned = sp2.autotune(n, args.precision)
+        sp2.autotune_reset()
+        out["autotune"] = {"tile": tuned["tile"], "kernel": tuned["kernel"], "layer_ms": round(tuned["ms"], 4),
+                           "headline_schedule": {"tile": info["tile"], "kernel": info["kernel"]}}
+        log("autotuner: tile %d kernel %d %.3f ms per layer (headline: tile %d kernel %d)"
+            % (tuned["tile"], tuned["kernel"], tuned["ms"], info["tile"], info["kernel"]))
     print(json.dumps(out), flush=True)
 
 
