@@ -409,6 +409,23 @@ def bench_batched(args):
                      "frac": round(value / PEAK_FP16_TFLOPS, 4), "traffic": None,
                      "kernel": "whole batched call (grouped squaring kernels dominate)"},
     }
+    if not args.no_accel:
+        # the same batch with each problem's HOMO/LUMO values (sp2_density_batched_gap)
+        gaps = [(w.homo, w.lumo) for w in ws]
+        souts = [torch.empty_like(h) for h in hs]
+        sp2.density_batched(hs, occ, precision=args.precision, outs=souts, workspace=wsbuf, gaps=gaps)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        for _ in range(args.steps):
+            _, ainfos = sp2.density_batched(hs, occ, precision=args.precision, outs=souts, workspace=wsbuf, gaps=gaps)
+        torch.cuda.synchronize()
+        ams = (time.perf_counter() - t3) * 1e3 / args.steps
+        out["accelerated"] = {"ms_per_call": round(ams, 3), "speedup_vs_plain": round(ms / ams, 3),
+                              "layers": {"min": min(i["layers"] for i in ainfos),
+                                         "max": max(i["layers"] for i in ainfos)},
+                              "status": sorted(set(i["status_name"] for i in ainfos))}
+        log("batched accelerated: %.2f ms per call, layers %d..%d" % (ams, out["accelerated"]["layers"]["min"],
+                                                                     out["accelerated"]["layers"]["max"]))
     if not args.no_cpu_baseline:
         from oracle import dm as odm
         from oracle import sp2 as osp2
@@ -425,6 +442,11 @@ def bench_batched(args):
                 for w, d in zip(ws, outs)]
         out["accuracy"] = {"max_fro_error_over_sqrt_n": max(errs), "bound_over_sqrt_n": 1e-3,
                            "max_trace_error": max(abs(i["trace"] - w.n_occ) for i, w in zip(infos, ws))}
+        if "accelerated" in out:
+            aerrs = [float(np.linalg.norm(d.cpu().numpy() - odm.dm_construct(w.q, w.eps, w.n_occ))) / np.sqrt(w.n)
+                     for w, d in zip(ws, souts)]
+            out["accelerated"]["max_fro_error_over_sqrt_n"] = max(aerrs)
+            out["accelerated"]["max_trace_error"] = max(abs(i["trace"] - w.n_occ) for i, w in zip(ainfos, ws))
     print(json.dumps(out), flush=True)
 
 

@@ -230,6 +230,18 @@ int sp2_density_batched(int batch, const double* const* dH, const int* ldh, doub
                         size_t work_bytes, void* stream);
 
 /*
+ * sp2_density_batched_gap -- sp2_density_batched with accelerated layers (Sec. Accelerated
+ * Deep-NN SP2) for every problem: homo[i] < lumo[i] (host arrays, finite) is an interval
+ * inside the HOMO-LUMO gap of H_i, as opt->homo/lumo of sp2_density with accelerate set;
+ * opt->accelerate itself must be 0.  Each problem's result is the one sp2_density gives
+ * with those options.  Same workspace as sp2_density_batched.
+ */
+int sp2_density_batched_gap(int batch, const double* const* dH, const int* ldh, double* const* dD,
+                            const int* ldd, const int* n, const int* n_occ, const double* homo,
+                            const double* lumo, double tol, const sp2_options* opt, sp2_info* infos,
+                            int use_graph, void* dWork, size_t work_bytes, void* stream);
+
+/*
  * Autotuner.  The automatic choices of sp2_density (tile = 0 and kernel = 0) and of
  * sp2_density_batched (tile = 0) come from a built-in rule unless the autotuner has
  * measured this case on the current device in this process; then its fastest choice is

@@ -953,16 +953,23 @@ size_t sp2_batched_workspace_size(int batch, const int* n, const sp2_options* op
     return L.total;
 }
 
-int sp2_density_batched(int batch, const double* const* dH, const int* ldh, double* const* dD, const int* ldd,
-                        const int* n, const int* n_occ, double tol, const sp2_options* opt, sp2_info* infos,
-                        int use_graph, void* dWork, size_t work_bytes, void* stream) {
+}  // extern "C"
+
+// The batched driver; homo/lumo (host, one per problem, or null) select accelerated layers.
+static int run_batched(int batch, const double* const* dH, const int* ldh, double* const* dD, const int* ldd,
+                       const int* n, const int* n_occ, const double* homo, const double* lumo, double tol,
+                       const sp2_options* opt, sp2_info* infos, int use_graph, void* dWork, size_t work_bytes,
+                       void* stream) {
     Opts o;
     if (batch <= 0 || !dH || !ldh || !dD || !ldd || !n || !n_occ || !dWork || !batch_opts(opt, &o)) return SP2_EINVAL;
     if (((uintptr_t)dWork) % kAlign) return SP2_EINVAL;
-    for (int i = 0; i < batch; ++i)
+    if ((homo == nullptr) != (lumo == nullptr)) return SP2_EINVAL;
+    for (int i = 0; i < batch; ++i) {
         if (!dH[i] || !dD[i] || n[i] <= 0 || n[i] > 65536 || ldh[i] < n[i] || ldd[i] < n[i] || n_occ[i] < 0 ||
             n_occ[i] > n[i])
             return SP2_EINVAL;
+        if (homo && !(isfinite(homo[i]) && isfinite(lumo[i]) && homo[i] < lumo[i])) return SP2_EINVAL;
+    }
     BatchLayout L;
     batch_layout(batch, n, n_occ, o, &L);
     if (work_bytes < L.total) return SP2_ENOMEM;
@@ -1063,6 +1070,11 @@ int sp2_density_batched(int batch, const double* const* dH, const int* ldh, doub
                 a.per = p.ref_per;
             }
             states[k] = initial_state(n[i], n_occ[i], tol, o, p);
+            if (homo) {
+                states[k].accel = 1;
+                states[k].homo = homo[i];
+                states[k].lumo = lumo[i];
+            }
         }
         // uploads (synchronous, before anything of this call is enqueued)
         SP2_TRY(hipStreamSynchronize(user));
@@ -1135,6 +1147,24 @@ int sp2_density_batched(int batch, const double* const* dH, const int* ldh, doub
         if (host.status != SP2_OK && worst == SP2_OK) worst = host.status;
     }
     return worst;
+}
+
+extern "C" {
+
+int sp2_density_batched(int batch, const double* const* dH, const int* ldh, double* const* dD, const int* ldd,
+                        const int* n, const int* n_occ, double tol, const sp2_options* opt, sp2_info* infos,
+                        int use_graph, void* dWork, size_t work_bytes, void* stream) {
+    return run_batched(batch, dH, ldh, dD, ldd, n, n_occ, nullptr, nullptr, tol, opt, infos, use_graph, dWork,
+                       work_bytes, stream);
+}
+
+int sp2_density_batched_gap(int batch, const double* const* dH, const int* ldh, double* const* dD, const int* ldd,
+                            const int* n, const int* n_occ, const double* homo, const double* lumo, double tol,
+                            const sp2_options* opt, sp2_info* infos, int use_graph, void* dWork, size_t work_bytes,
+                            void* stream) {
+    if (!homo || !lumo) return SP2_EINVAL;
+    return run_batched(batch, dH, ldh, dD, ldd, n, n_occ, homo, lumo, tol, opt, infos, use_graph, dWork, work_bytes,
+                       stream);
 }
 
 }  // extern "C"

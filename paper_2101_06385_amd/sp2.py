@@ -124,6 +124,12 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(c_int), c_double, ctypes.POINTER(Options),
                                       ctypes.POINTER(Info), c_int, c_void_p, c_size_t, c_void_p]
     L.sp2_density_batched.restype = c_int
+    L.sp2_density_batched_gap.argtypes = [c_int, ctypes.POINTER(c_void_p), ctypes.POINTER(c_int),
+                                          ctypes.POINTER(c_void_p), ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                                          ctypes.POINTER(c_int), ctypes.POINTER(c_double), ctypes.POINTER(c_double),
+                                          c_double, ctypes.POINTER(Options), ctypes.POINTER(Info), c_int, c_void_p,
+                                          c_size_t, c_void_p]
+    L.sp2_density_batched_gap.restype = c_int
     L.sp2_autotune_workspace_size.argtypes = [c_int, c_int]
     L.sp2_autotune_workspace_size.restype = c_size_t
     L.sp2_autotune.argtypes = [c_int, c_int, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
@@ -314,9 +320,10 @@ def batched_workspace_size(sizes, opts: Optional[Options] = None) -> int:
 
 
 def density_batched(hs, n_occs, tol: float = 0.0, precision="fp16x2", max_layers=100, eps=0.0, scale_log2=-1,
-                    want_energy=False, tile=0, use_graph=True, outs=None, workspace=None, stream=None):
+                    want_energy=False, tile=0, use_graph=True, outs=None, workspace=None, stream=None, gaps=None):
     """D_i = theta(mu_i I - H_i) for a list of symmetric FP64 CUDA tensors of any sizes, all
-    problems advanced together one layer per launch.  Returns (list of D_i, list of info)."""
+    problems advanced together one layer per launch.  gaps: one (homo, lumo) per problem
+    for accelerated layers (sp2_density_batched_gap).  Returns (list of D_i, list of info)."""
     import torch
 
     b = len(hs)
@@ -343,9 +350,18 @@ def density_batched(hs, n_occs, tol: float = 0.0, precision="fp16x2", max_layers
     ld = (ctypes.c_int * b)(*[d.stride(0) for d in outs])
     nn = (ctypes.c_int * b)(*sizes)
     no = (ctypes.c_int * b)(*[int(v) for v in n_occs])
-    st = lib().sp2_density_batched(b, ph, lh, pd, ld, nn, no, float(tol), ctypes.byref(opts), infos,
-                                   1 if use_graph else 0, ctypes.c_void_p(workspace.data_ptr()),
-                                   workspace.numel(), _stream_ptr(dev, stream))
+    if gaps is not None:
+        if len(gaps) != b:
+            raise ValueError("need one (homo, lumo) per Hamiltonian")
+        ho = (ctypes.c_double * b)(*[float(g[0]) for g in gaps])
+        lu = (ctypes.c_double * b)(*[float(g[1]) for g in gaps])
+        st = lib().sp2_density_batched_gap(b, ph, lh, pd, ld, nn, no, ho, lu, float(tol), ctypes.byref(opts), infos,
+                                           1 if use_graph else 0, ctypes.c_void_p(workspace.data_ptr()),
+                                           workspace.numel(), _stream_ptr(dev, stream))
+    else:
+        st = lib().sp2_density_batched(b, ph, lh, pd, ld, nn, no, float(tol), ctypes.byref(opts), infos,
+                                       1 if use_graph else 0, ctypes.c_void_p(workspace.data_ptr()),
+                                       workspace.numel(), _stream_ptr(dev, stream))
     if st in (SP2_EDEVICE, SP2_ENOMEM) or (st == SP2_EINVAL and all(int(i.n_padded) == 0 for i in infos)):
         raise SP2Error(st, "sp2_density_batched")
     return outs, [info_dict(i) for i in infos]

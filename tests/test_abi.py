@@ -168,6 +168,16 @@ def test_batched_workspace_and_argument_errors():
     assert call(10, 5, 10, 10, work=16) == sp2.SP2_ENOMEM
     assert L.sp2_density_batched(0, ph, I(10), pd, I(10), I(10), I(5), 0.0, ctypes.byref(o), None, 1, fake,
                                  1 << 40, None) == sp2.SP2_EINVAL
+    D = ctypes.c_double * 1
+
+    def call_gap(homo, lumo):
+        return L.sp2_density_batched_gap(1, ph, I(10), pd, I(10), I(10), I(5), homo, lumo, 0.0, ctypes.byref(o), None,
+                                         1, fake, 16, None)
+
+    assert call_gap(D(1.0), D(-1.0)) == sp2.SP2_EINVAL          # homo >= lumo
+    assert call_gap(D(float("nan")), D(1.0)) == sp2.SP2_EINVAL
+    assert call_gap(None, D(1.0)) == sp2.SP2_EINVAL
+    assert call_gap(D(-1.0), D(1.0)) == sp2.SP2_ENOMEM          # valid interval: reaches the size check
 
 
 def test_autotune_sizes_and_argument_errors():

@@ -96,3 +96,30 @@ def test_batched_rejects_fp64_and_bounds():
     h = torch.eye(64, dtype=torch.float64, device=DEV)
     with pytest.raises(sp2.SP2Error):
         sp2.density_batched([h], [10], precision="fp64")
+
+
+@pytest.mark.parametrize("prec,tile,sizes", [("fp16x2", 64, (64, 130, 200, 257)), ("fp16x2", 128, (520, 700, 900)),
+                                             ("bf16x2", 64, (90, 300))])
+def test_batched_accelerated_matches_single_path_bitwise(prec, tile, sizes):
+    """sp2_density_batched_gap: every problem's accelerated run (its own HOMO/LUMO interval)
+    equals the single accelerated call with the same tile and schedule; a problem with an
+    empty occupation rides along."""
+    ws = [wl.gapped(70 + i, n, n // 3, occ_lo=-20.0, homo=-1.0 - 0.2 * i, lumo=1.0 + 0.1 * i, virt_hi=20.0)
+          for i, n in enumerate(sizes)]
+    hs = [torch.from_numpy(w.h).to(DEV) for w in ws]
+    occ = [w.n_occ for w in ws]
+    gaps = [(w.homo, w.lumo) for w in ws]
+    extra = wl.gapped(79, 96, 30)
+    hs.append(torch.from_numpy(extra.h).to(DEV))
+    occ.append(0)
+    gaps.append((-1.0, 1.0))
+    outs, infos = sp2.density_batched(hs, occ, precision=prec, tile=tile, gaps=gaps)
+    for w, h, d, info, g in zip(ws, hs, outs, infos, gaps):
+        d1, i1 = sp2.density(h, w.n_occ, precision=prec, tile=tile, kernel=1, gap=g)
+        assert info["accelerated"] == i1["accelerated"] > 0
+        assert info["layers"] == i1["layers"] and info["sigma"] == i1["sigma"]
+        assert info["sigma_c"] == i1["sigma_c"]
+        assert torch.equal(d, d1), w.name
+        if prec == "fp16x2":
+            _check_vs_oracle(w, d, info)
+    assert infos[-1]["status"] == 0 and torch.count_nonzero(outs[-1]).item() == 0
