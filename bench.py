@@ -126,7 +126,7 @@ def main():
                          "the 11-layer optimized finite-temperature expansion at N (default 8192)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the path runs on one MI355X); "
+        print("bench.py: the SP2 path runs on one MI355X and is measured on one GPU; "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched":
