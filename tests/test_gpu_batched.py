@@ -123,3 +123,14 @@ def test_batched_accelerated_matches_single_path_bitwise(prec, tile, sizes):
         if prec == "fp16x2":
             _check_vs_oracle(w, d, info)
     assert infos[-1]["status"] == 0 and torch.count_nonzero(outs[-1]).item() == 0
+
+
+def test_batched_config4_full_vs_oracle():
+    """All 64 problems of the batched workload (N_i = 64 U{4..48}), one call, each against its
+    eigendecomposition."""
+    ws = wl.config4(device=DEV)
+    hs = [torch.from_numpy(w.h).to(DEV) for w in ws]
+    outs, infos = sp2.density_batched(hs, [w.n_occ for w in ws])
+    assert len(outs) == 64
+    for w, d, info in zip(ws, outs, infos):
+        _check_vs_oracle(w, d, info)

@@ -7,6 +7,8 @@ epilogue, with u = 2^-24 and K the product length.  FP32/FP64 modes: the same bo
 |X||X|.  Every result must be bitwise symmetric, and the FP64 tile sums must equal the
 trace and squared Frobenius norm of the returned matrix.
 """
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -26,10 +28,16 @@ def _state(n, seed):
 
 
 def _check_sums(y, sums):
-    tr = float(np.trace(y))
-    fr = float(np.sum(y * y))
-    assert abs(sums[0] - tr) <= 1e-12 * max(1.0, abs(tr))
-    assert abs(sums[1] - fr) <= 1e-12 * max(1.0, abs(fr))
+    """The device's FP64 tile sums of Tr Y and ||Y||_F^2 against math.fsum (the exactly
+    rounded sums of the same stored values; squares of FP32 values are exact in FP64):
+    any order of FP64 additions of m terms is within (m - 1) 2^-53 sum |terms|."""
+    y = np.asarray(y, dtype=np.float64)
+    d = np.diag(y)
+    sq = (y * y).ravel()
+    tr = math.fsum(d)
+    fr = math.fsum(sq)
+    assert abs(sums[0] - tr) <= d.size * 2.0 ** -53 * math.fsum(np.abs(d)) + 1e-300
+    assert abs(sums[1] - fr) <= sq.size * 2.0 ** -53 * fr + 1e-300
 
 
 @pytest.mark.parametrize("prec,tile,n", [

@@ -459,3 +459,39 @@ def test_sp2_accelerated_tiny_systems_brute_force():
         expect = (np.arange(n) >= n - n_occ).astype(float)
         assert res.converged
         assert np.abs(res.d - expect).max() < 1e-9, (n, n_occ, l, h, res.layers)
+
+
+def test_trace_idempotency_bounds_the_spectral_norm():
+    """Sec. Deep-NN SP2: for eigenvalues in [0, 1],
+    ||X - X^2||_2 <= Tr[X - X^2] <= N ||X - X^2||_2 (on random spectra and on SP2 layers)."""
+    rng = np.random.default_rng(17)
+    mats = []
+    for n in (5, 40, 120):
+        q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        lam = rng.uniform(0.0, 1.0, n)
+        mats.append((q * lam) @ q.T)
+    w = wl.gapped(18, 80, 30)
+    e1, en = sp2.gershgorin(w.h)
+    s = sp2.rescale(w.h, e1, en)
+    for k in range(6):
+        mats.append(s)
+        s = s @ s if k % 2 == 0 else 2 * s - s @ s
+    for x in mats:
+        x = 0.5 * (x + x.T)
+        e = x - x @ x
+        spec = np.abs(np.linalg.eigvalsh(e)).max()
+        tr = np.trace(e)
+        assert spec <= tr + 1e-12 and tr <= x.shape[0] * spec + 1e-12
+
+
+def test_ns_recurrence_equals_the_trace():
+    """Alg. 1 keeps N_S by the recurrence sigma N_X + (1 - sigma) N_S; in exact arithmetic it
+    is Tr S_n.  Along an FP64 run both agree to rounding."""
+    w = wl.gapped(19, 150, 40)
+    e1, en = sp2.gershgorin(w.h)
+    s = sp2.rescale(w.h, e1, en)
+    res = sp2.sp2_alg1(w.h, w.n_occ)
+    for k in range(res.layers - 1):
+        assert abs(res.ns[k] - np.trace(s)) <= 1e-10 * max(1.0, np.trace(s)), k
+        x = s @ s
+        s = x if res.sigma[k] > 0 else 2 * s - x
