@@ -360,13 +360,14 @@ def homo_lumo_rescaled(homo: float, lumo: float, e1: float, en: float):
 @dataclass
 class SP2AccResult(SP2Result):
     accelerated: int = 0                             # layers 1..accelerated used sigma_n in R
+    gap_violation: int = 0                           # first layer whose consistency check failed
     sigma_c: list = field(default_factory=list)     # continuous sigma_n of layer n
     lh: list = field(default_factory=list)           # (l, h) entering layer n
 
 
 def sp2_accelerated(h: np.ndarray, n_occ: int, homo: float, lumo: float, bounds=None, eps: float = 0.0,
                     max_layers: int = 100, activation: Callable = square_fp64, refine: bool = True,
-                    switch: float = ACCEL_SWITCH) -> SP2AccResult:
+                    switch: float = ACCEL_SWITCH, noise_rel: float = 1e-8) -> SP2AccResult:
     """Accelerated Deep-NN SP2 on the matrix H.
 
     Every occupied eigenvalue of H is <= homo and every unoccupied one >= lumo (an
@@ -376,6 +377,12 @@ def sp2_accelerated(h: np.ndarray, n_occ: int, homo: float, lumo: float, bounds=
     that its second clause compares IdErr_n with IdErr_{n-2} only when the two layers
     between them were ordinary SP2 layers (the bound behind it holds for x^2 and
     2x - x^2).  The refinement is Eq. Refinement, as for Alg. 1.
+
+    Consistency of the interval: if it lies inside the gap, exactly N_occ eigenvalues of S_0
+    are in [h, 1] and the rest in [0, l]; every layer (accelerated or not) maps those
+    intervals onto the tracked ones, so |Tr S_{n-1} - N_occ| <= (N - N_occ) l + N_occ (1 - h)
+    at every layer.  The first layer where this fails by more than noise_rel N is recorded
+    in `gap_violation` (the interval was not inside the gap).
     """
     h = np.asarray(h, dtype=np.float64)
     e1, en = bounds if bounds is not None else gershgorin(h)
@@ -400,6 +407,10 @@ def sp2_accelerated(h: np.ndarray, n_occ: int, homo: float, lumo: float, bounds=
         res.nx.append(n_x)
         res.iderr.append(e_n)
         res.lh.append((l, hh))
+        nn = h.shape[0]
+        if accel and not res.gap_violation and \
+                abs(n_s - n_occ) > (nn - n_occ) * l + n_occ * (1.0 - hh) + noise_rel * nn:
+            res.gap_violation = n
         if accel and max(l, 1.0 - hh) > switch:
             sigma, w, bs, bi, l, hh = accelerated_layer(l, hh)
             s_sign = 1 if sigma > 0 else -1
@@ -410,6 +421,8 @@ def sp2_accelerated(h: np.ndarray, n_occ: int, homo: float, lumo: float, bounds=
             s_sign = sign_with_tie(v, sig[n - 1])
             sigma = float(s_sign)
             s_new = s_sign * x + (1 - s_sign) * s_prev
+            if accel:   # the tracked intervals follow the SP2 maps too
+                l, hh = (l * l, hh * hh) if s_sign > 0 else (2.0 * l - l * l, 2.0 * hh - hh * hh)
         res.sigma.append(s_sign)
         res.sigma_c.append(sigma)
         sig.append(s_sign)
@@ -430,7 +443,8 @@ def sp2_accelerated(h: np.ndarray, n_occ: int, homo: float, lumo: float, bounds=
 
 
 def sp2_eigen_accelerated(lam0: np.ndarray, n_occ: int, l0: float, h0: float, eps: float = 0.0,
-                          max_layers: int = 100, switch: float = ACCEL_SWITCH) -> SP2AccResult:
+                          max_layers: int = 100, switch: float = ACCEL_SWITCH,
+                          noise_rel: float = 1e-8) -> SP2AccResult:
     """`sp2_accelerated` on the eigenvalues of S_0 (each layer is a quadratic in S_{n-1},
     so the eigenvalues follow the scalar maps).  FP64, O(N m).  `d` holds the refined
     eigenvalues."""
@@ -455,6 +469,10 @@ def sp2_eigen_accelerated(lam0: np.ndarray, n_occ: int, l0: float, h0: float, ep
         res.nx.append(n_x)
         res.iderr.append(e_n)
         res.lh.append((l, hh))
+        nn = lam.size
+        if accel and not res.gap_violation and \
+                abs(n_s - n_occ) > (nn - n_occ) * l + n_occ * (1.0 - hh) + noise_rel * nn:
+            res.gap_violation = n
         if accel and max(l, 1.0 - hh) > switch:
             sigma, w, bs, bi, l, hh = accelerated_layer(l, hh)
             s_sign = 1 if sigma > 0 else -1
@@ -465,6 +483,8 @@ def sp2_eigen_accelerated(lam0: np.ndarray, n_occ: int, l0: float, h0: float, ep
             s_sign = sign_with_tie(v, sig[n - 1])
             sigma = float(s_sign)
             new = x if s_sign > 0 else 2.0 * lam - x
+            if accel:
+                l, hh = (l * l, hh * hh) if s_sign > 0 else (2.0 * l - l * l, 2.0 * hh - hh * hh)
         res.sigma.append(s_sign)
         res.sigma_c.append(sigma)
         sig.append(s_sign)

@@ -495,3 +495,54 @@ def test_ns_recurrence_equals_the_trace():
         assert abs(res.ns[k] - np.trace(s)) <= 1e-10 * max(1.0, np.trace(s)), k
         x = s @ s
         s = x if res.sigma[k] > 0 else 2 * s - x
+
+
+def test_gap_check_flags_every_wrong_result_brute_force():
+    """Random intervals, valid or not, on small spectra: whenever the accelerated run ends
+    on the wrong projector the interval check has fired, and it never fires for an
+    interval that lies inside the gap."""
+    rng = np.random.default_rng(43)
+    wrong_seen = 0
+    for _ in range(1500):
+        n = int(rng.integers(2, 40))
+        n_occ = int(rng.integers(1, n))
+        gap = 10 ** rng.uniform(-4, -0.5)
+        c = rng.uniform(0.01 + gap, 0.99 - gap)
+        lt, ht = c - gap / 2, c + gap / 2
+        un = np.sort(rng.uniform(0.0, lt, n - n_occ))
+        un[-1] = lt
+        oc = np.sort(rng.uniform(ht, 1.0, n_occ))
+        oc[0] = ht
+        lam0 = np.concatenate([un, oc])
+        if rng.uniform() < 0.5:
+            a, b = rng.uniform(lt, c), rng.uniform(c, ht)          # inside the gap
+        else:
+            a, b = np.sort(rng.uniform(0.0, 1.0, 2))               # anywhere
+        res = sp2.sp2_eigen_accelerated(lam0, n_occ, float(a), float(b))
+        expect = (np.arange(n) >= n - n_occ).astype(float)
+        wrong = np.abs(res.d - expect).max() > 0.5
+        wrong_seen += wrong
+        if wrong:
+            assert res.gap_violation > 0, (n, n_occ, lt, ht, a, b)
+        if lt <= a < b <= ht:
+            assert res.gap_violation == 0, (n, n_occ, lt, ht, a, b)
+    assert wrong_seen > 50      # the sample does contain intervals that break the result
+
+
+def test_gap_check_silent_for_valid_intervals():
+    """Intervals inside the gap on the workloads' spectra (Gershgorin and exact bounds)."""
+    for w in _acc_cases():
+        for bounds in (None, (float(w.eps[0]), float(w.eps[-1]))):
+            for f in (0.0, 0.3, 0.9):
+                homo = w.homo + f * 0.5 * (w.lumo - w.homo)
+                lumo = w.lumo - f * 0.5 * (w.lumo - w.homo)
+                res = sp2.sp2_accelerated(w.h, w.n_occ, homo, lumo, bounds=bounds)
+                assert res.gap_violation == 0
+                assert res.accelerated > 0
+
+
+def test_gap_check_fires_for_an_interval_inside_a_band():
+    w = _acc_cases()[0]        # occupied band [-20, -1], virtual [1, 20]
+    for homo, lumo in ((-10.0, -5.0), (5.0, 10.0)):
+        res = sp2.sp2_accelerated(w.h, w.n_occ, homo, lumo)
+        assert res.gap_violation > 0
