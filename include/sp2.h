@@ -95,12 +95,15 @@ typedef struct {
                           without crossing.  Once max(l, 1 - h) <= 0.01 the layers of Alg. 1
                           continue; its alternation stopping test is taken only across two
                           such layers.  If homo/lumo do not rescale into 0 <= l < h <= 1 no
-                          layer is accelerated (sp2_info.accelerated = 0).  Single-problem
-                          calls only (the batched call rejects it). */
+                          layer is accelerated (sp2_info.accelerated = 0).  Every layer
+                          checks the interval against Tr S (sp2_info.gap_violation).
+                          Single-problem calls (sp2_density_batched_gap for batches). */
     double homo, lumo; /* with accelerate: every occupied eigenvalue of H is <= homo and every
                           unoccupied one >= lumo, homo < lumo (an interval inside the
-                          HOMO-LUMO gap, e.g. from a previous call); values outside the true
-                          gap can make the result wrong, which the final check reports */
+                          HOMO-LUMO gap, e.g. from a previous call).  An interval that is not
+                          inside the gap can end on the projector onto the wrong states (with
+                          the right trace); the per-layer consistency check reports that as
+                          SP2_ENOTIDEMP with sp2_info.gap_violation > 0. */
 } sp2_options;
 
 typedef struct {
@@ -114,6 +117,11 @@ typedef struct {
                               FP32/FP64 run), 8 = the register-staged per-tile kernel,
                               2 + v = persistent schedule, variant v */
     int accelerated;       /* number of accelerated layers (they are layers 1..accelerated) */
+    int gap_violation;     /* accelerated runs: first layer n where |Tr S_{n-1} - n_occ| exceeded
+                              (n - n_occ) l + n_occ (1 - h) (the tracked interval bounds) by more
+                              than rounding, i.e. [homo, lumo] was not inside the gap; 0 if never.
+                              A violation makes the status SP2_ENOTIDEMP. */
+    int reserved;
     double emin, emax;     /* spectral bounds used */
     double trace;          /* Tr D */
     double idem;           /* Tr D - ||D||_F^2  (= Tr[D - D^2] for symmetric D) */

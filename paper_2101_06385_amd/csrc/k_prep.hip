@@ -94,6 +94,8 @@ __global__ void k_state_init(DevState* st, StateParams p) {
         st->energy = 0.0;
         st->accel = p.accel;
         st->acc_layers = 0;
+        st->gap_violation = 0;
+        st->pad2 = 0;
         st->homo = p.homo;
         st->lumo = p.lumo;
         st->acc_l = 0.0;
@@ -356,6 +358,15 @@ __device__ __forceinline__ void control_body(DevState* st, const double* __restr
                 st->accel = 0;
             }
         }
+        // Interval consistency: inside the gap, exactly n_occ eigenvalues start in [h, 1] and
+        // every layer maps the tracked intervals onto the next ones, so Tr S_{n-1} lies within
+        // (N - n_occ) l + n_occ (1 - h) of n_occ; a larger distance (beyond rounding) means the
+        // interval was not inside the gap.
+        if (st->accel && st->gap_violation == 0) {
+            const double nn = (double)st->n, occ = (double)st->n_occ;
+            const double noise = (st->precision == SP2_FP64 ? 1e-8 : 1e-3) * nn;
+            if (fabs(n_s - occ) > (nn - occ) * st->acc_l + occ * (1.0 - st->acc_h) + noise) st->gap_violation = n;
+        }
         int s;
         double ca, cb, cc, sc;
         if (st->accel && fmax(st->acc_l, 1.0 - st->acc_h) > kAccSwitch) {
@@ -372,6 +383,11 @@ __device__ __forceinline__ void control_body(DevState* st, const double* __restr
             cb = s > 0 ? 0.0 : 2.0;
             cc = 0.0;
             sc = (double)s;
+            if (st->accel) {   // the tracked intervals follow the SP2 maps too
+                const double l = st->acc_l, h = st->acc_h;
+                st->acc_l = s > 0 ? l * l : 2.0 * l - l * l;
+                st->acc_h = s > 0 ? h * h : 2.0 * h - h * h;
+            }
         }
         st->sigma[n] = (signed char)s;
         st->sigma_c[n] = sc;
@@ -483,6 +499,7 @@ __device__ __forceinline__ void finalize_body(DevState* st, const double* __rest
     if (status == SP2_OK) {
         const double idem = v[0] - v[1];
         if (!isfinite(v[0]) || !isfinite(v[1])) status = SP2_ENONFINITE;
+        else if (st->gap_violation) status = SP2_ENOTIDEMP;   // the interval was not inside the gap
         else if (!st->converged) status = SP2_ENOCONV;
         else if (!(fabs(v[0] - st->n_occ) <= st->tol_tr) || !(fabs(idem) <= st->tol_id)) status = SP2_ENOTIDEMP;
     }

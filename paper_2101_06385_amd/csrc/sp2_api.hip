@@ -238,6 +238,7 @@ void fill_info(const DevState& st, const Plan* p, sp2_info* info) {
         info->sigma_c[k - 1] = st.sigma_c[k];
     }
     info->accelerated = st.acc_layers;
+    info->gap_violation = st.gap_violation;
     if (p) {
         StreamK sk;
         int variant = 0;

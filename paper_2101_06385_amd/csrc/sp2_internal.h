@@ -38,8 +38,10 @@ struct DevState {
     double ns[SP2_MAX_LAYERS + 1];
     double nx[SP2_MAX_LAYERS + 1];
     // accelerated layers (Sec. Accelerated Deep-NN SP2)
-    int accel;          // 1 while accelerated layers may still be chosen
+    int accel;          // 1 when the caller's interval rescaled into 0 <= l < h <= 1
     int acc_layers;     // index of the last accelerated layer (0: none)
+    int gap_violation;  // first layer whose interval consistency check failed (0: none)
+    int pad2;
     double homo, lumo;  // caller's interval inside the gap (energies)
     double acc_l, acc_h;  // unoccupied eigenvalues of S_{n-1} in [0, acc_l], occupied in [acc_h, 1]
     double sigma_c[SP2_MAX_LAYERS + 1];

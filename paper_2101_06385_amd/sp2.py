@@ -51,6 +51,8 @@ class Info(ctypes.Structure):
         ("tile", ctypes.c_int),
         ("kernel", ctypes.c_int),
         ("accelerated", ctypes.c_int),
+        ("gap_violation", ctypes.c_int),
+        ("reserved", ctypes.c_int),
         ("emin", ctypes.c_double),
         ("emax", ctypes.c_double),
         ("trace", ctypes.c_double),
@@ -248,6 +250,7 @@ def info_dict(info: Info) -> dict:
         "ns": [float(info.ns[i]) for i in range(m)],
         "nx": [float(info.nx[i]) for i in range(m)],
         "accelerated": int(info.accelerated),
+        "gap_violation": int(info.gap_violation),
         "sigma_c": [float(info.sigma_c[i]) for i in range(m)],
     }
 

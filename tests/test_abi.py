@@ -46,14 +46,14 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
         '#include <stddef.h>\n#include <stdio.h>\n#include "sp2.h"\n'
         "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(sp2_options), sizeof(sp2_info),"
         " offsetof(sp2_options, tile), offsetof(sp2_info, sigma), offsetof(sp2_info, iderr),"
-        " offsetof(sp2_info, nx), offsetof(sp2_options, homo), offsetof(sp2_info, accelerated),"
+        " offsetof(sp2_info, nx), offsetof(sp2_options, homo), offsetof(sp2_info, gap_violation),"
         " offsetof(sp2_info, sigma_c));return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [ctypes.sizeof(sp2.Options), ctypes.sizeof(sp2.Info), sp2.Options.tile.offset,
             sp2.Info.sigma.offset, sp2.Info.iderr.offset, sp2.Info.nx.offset, sp2.Options.homo.offset,
-            sp2.Info.accelerated.offset, sp2.Info.sigma_c.offset]
+            sp2.Info.gap_violation.offset, sp2.Info.sigma_c.offset]
     assert got == want
 
 

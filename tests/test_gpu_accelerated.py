@@ -26,6 +26,7 @@ def _run(h, n_occ, **kw):
 def _check_accelerated_history(info, ref):
     k = ref.accelerated
     assert k > 0 and info["accelerated"] == k, (info["accelerated"], k)
+    assert info["gap_violation"] == 0 and ref.gap_violation == 0
     assert info["sigma"][:k] == ref.sigma[:k]
     got = np.array(info["sigma_c"][:k])
     assert np.allclose(got, ref.sigma_c[:k], rtol=1e-12, atol=0.0), (got, ref.sigma_c[:k])
@@ -122,3 +123,20 @@ def test_tiny_spectra_accelerated_fp64():
         ref = osp2.sp2_accelerated(hm, n_occ, homo, lumo, bounds=(0.0, 1.0))
         assert np.abs(d - dm.dm_construct(q, eps, n_occ)).max() < 1e-9, (n, n_occ, l, h)
         assert info["accelerated"] == ref.accelerated and info["sigma"][:ref.accelerated] == ref.sigma[:ref.accelerated]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16x2"])
+def test_interval_inside_a_band_is_reported(prec):
+    """An interval inside the occupied or the virtual band (not inside the gap) ends on an
+    idempotent projector with the right trace but onto the wrong states; the per-layer
+    interval check must report it (SP2_ENOTIDEMP, gap_violation > 0), at the layer the
+    oracle's check names in FP64."""
+    w = wl.gapped(91, 400, 100, occ_lo=-20.0, homo=-1.0, lumo=1.0, virt_hi=20.0)
+    for homo, lumo in ((-10.0, -5.0), (5.0, 10.0)):
+        d, info = _run(w.h, w.n_occ, precision=prec, gap=(homo, lumo))
+        ref = osp2.sp2_accelerated(w.h, w.n_occ, homo, lumo)
+        assert ref.gap_violation > 0
+        assert info["status"] == sp2.SP2_ENOTIDEMP, info["status_name"]
+        assert info["gap_violation"] > 0
+        if prec == "fp64":
+            assert info["gap_violation"] == ref.gap_violation
