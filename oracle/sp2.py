@@ -507,3 +507,63 @@ def sp2_eigen_accelerated(lam0: np.ndarray, n_occ: int, l0: float, h0: float, ep
         y = 2.0 * lam - lam * lam
         res.d = y * y
     return res
+
+
+# --------------------------------------------------------------------------------------
+# HOMO/LUMO estimates from a finished expansion (for the accelerated layers of a later
+# call, Sec. Accelerated Deep-NN SP2: the estimates can come from previous expansions)
+# --------------------------------------------------------------------------------------
+def estimate_gap(sigma_c, iderr, layers: int, emin: float, emax: float, n: int, floor_rel: float,
+                 upper: float = 0.25, margin: float = 0.1):
+    """(homo, lumo) estimated from the history of a converged run, or None.
+
+    Reading (the section refers to this possibility without a method): near convergence
+    IdErr_k = Tr[S_{k-1} - S_{k-1}^2] is dominated by the two eigenvalues nearest the step,
+    the LUMO image a (near 0) and the HOMO image 1 - c (near 1): IdErr_k ~ a + c.  An
+    ordinary layer maps (a, c) to (a^2, 2c - c^2) (x^2) or (2a - a^2, c^2) (2x - x^2), so two
+    consecutive values give a quadratic for a (x^2: a^2 - 2a + (2 IdErr_k - IdErr_{k+1}) = 0)
+    and c = IdErr_k - a (the 2x - x^2 case with the roles exchanged).  The layer maps before
+    S_{k-1} (sigma_n, with the shift v = (1 - 1/|sigma_n|)/2 of an accelerated layer) are
+    inverted exactly on their increasing branch, and S_0 = (emax I - H)/(emax - emin) gives the
+    energies.  Other eigenvalues near the step add to IdErr and move both estimates toward
+    the middle of the gap.  Every consecutive pair with IdErr_k <= upper, IdErr_{k+1} >=
+    floor_rel n and an ordinary layer k contributes; the highest HOMO and the lowest LUMO
+    estimate are kept, then each is moved inward by `margin` times their distance.
+    """
+    maps = []
+    for s in list(sigma_c)[:max(layers - 1, 0)]:
+        b = 1 if s > 0 else -1
+        maps.append((b, 0.5 * (1.0 - 1.0 / abs(s))))
+
+    def inverse(y, b, v):
+        y = min(max(y, 0.0), 1.0)
+        if b > 0:                                   # y = ((x - v)/(1 - v))^2, x >= v
+            return v + (1.0 - v) * math.sqrt(y)
+        return (1.0 - v) * (1.0 - math.sqrt(1.0 - y))   # y = 1 - ((1 - v - x)/(1 - v))^2
+
+    homos, lumos = [], []
+    span = emax - emin
+    for k in range(len(maps) - 1):
+        e0, e1 = iderr[k], iderr[k + 1]
+        b, v = maps[k]
+        if not (e0 <= upper and e1 >= floor_rel * n and v == 0.0):
+            continue
+        disc = 1.0 - (2.0 * e0 - e1)
+        if disc < 0.0:
+            continue
+        r = 1.0 - math.sqrt(disc)
+        a, c = (r, e0 - r) if b > 0 else (e0 - r, r)
+        if a <= 0.0 or c <= 0.0:
+            continue
+        xl, xh = a, 1.0 - c
+        for bb, vv in reversed(maps[:k]):
+            xl, xh = inverse(xl, bb, vv), inverse(xh, bb, vv)
+        homos.append(emax - xh * span)
+        lumos.append(emax - xl * span)
+    if not homos:
+        return None
+    homo, lumo = max(homos), min(lumos)
+    if lumo <= homo:
+        return None
+    w = lumo - homo
+    return homo + margin * w, lumo - margin * w

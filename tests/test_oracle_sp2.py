@@ -546,3 +546,53 @@ def test_gap_check_fires_for_an_interval_inside_a_band():
     for homo, lumo in ((-10.0, -5.0), (5.0, 10.0)):
         res = sp2.sp2_accelerated(w.h, w.n_occ, homo, lumo)
         assert res.gap_violation > 0
+
+
+def _spectrum(rng, n, n_occ, homo, gap, lo=-20.0, hi=25.0):
+    occ = np.sort(rng.uniform(lo, homo, n_occ))
+    occ[-1] = homo
+    vir = np.sort(rng.uniform(homo + gap, hi, n - n_occ))
+    vir[0] = homo + gap
+    return np.concatenate([occ, vir])
+
+
+def test_gap_estimate_two_states_recovers_homo_lumo():
+    """One occupied and one virtual state: IdErr is exactly the two terms, so with a small
+    `upper` (leading order accurate) and no margin the estimate is the true pair; this pins
+    the quadratic solve and the inverse layer maps (plain and accelerated histories)."""
+    for homo, gap in ((-3.0, 0.7), (4.0, 0.05), (-10.0, 2.0)):
+        eps = np.array([homo, homo + gap])
+        e1, en = -25.0, 25.0
+        lam0 = (en - eps) / (en - e1)
+        for run in (sp2.sp2_eigen(lam0, 1),
+                    sp2.sp2_eigen_accelerated(lam0, 1, lam0[1] - 0.01 * gap / 50, lam0[0] + 0.01 * gap / 50)):
+            sc = getattr(run, "sigma_c", None) or [float(s) for s in run.sigma]
+            est = sp2.estimate_gap(sc, run.iderr, run.layers, e1, en, 2, 1e-14, upper=1e-3, margin=0.0)
+            assert est is not None
+            assert abs(est[0] - homo) < 1e-3 * gap and abs(est[1] - (homo + gap)) < 1e-3 * gap, (est, homo, gap)
+
+
+def test_gap_estimate_lies_inside_the_gap_brute_force():
+    """Random spectra (sizes, occupations, gap widths and positions), plain and accelerated
+    FP64 eigenvalue runs: every estimate lies inside the true gap."""
+    rng = np.random.default_rng(47)
+    got = 0
+    for t in range(300):
+        n = int(rng.integers(20, 800))
+        n_occ = int(rng.integers(1, n))
+        homo = rng.uniform(-15.0, 15.0)
+        gap = 10 ** rng.uniform(-2.0, 0.5)
+        eps = _spectrum(rng, n, n_occ, homo, gap)
+        e1, en = -30.0, 30.0
+        lam0 = (en - eps) / (en - e1)
+        runs = [sp2.sp2_eigen(lam0, n_occ)]
+        if t % 2:
+            runs.append(sp2.sp2_eigen_accelerated(lam0, n_occ, lam0[n_occ], lam0[n_occ - 1]))
+        for run in runs:
+            sc = getattr(run, "sigma_c", None) or [float(s) for s in run.sigma]
+            est = sp2.estimate_gap(sc, run.iderr, run.layers, e1, en, n, 1e-12)
+            if est is None:
+                continue
+            got += 1
+            assert homo <= est[0] < est[1] <= homo + gap, (n, n_occ, homo, gap, est)
+    assert got > 250
