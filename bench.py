@@ -120,10 +120,11 @@ def main():
     ap.add_argument("--no-accel", action="store_true", help="skip the accelerated Deep-NN SP2 leg")
     ap.add_argument("--no-autotune", action="store_true", help="skip reporting the autotuner's choice")
     ap.add_argument("--gen-device", default="cuda", help="where the QR of the workload generator runs")
-    ap.add_argument("--workload", default="density", choices=["density", "batched", "net", "fermi"],
+    ap.add_argument("--workload", default="density", choices=["density", "batched", "net", "fermi", "md"],
                     help="density: the N=8192 headline (default); batched: 64 Hamiltonians of uneven "
                          "sizes in one graph; net: the 20-layer differentiable network at N=2048; fermi: "
-                         "the 11-layer optimized finite-temperature expansion at N (default 8192)")
+                         "the 11-layer optimized finite-temperature expansion at N (default 8192); md: a "
+                         "sequence of slowly changing Hamiltonians with HOMO/LUMO estimates carried forward")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the SP2 path runs on one MI355X and is measured on one GPU; "
@@ -135,6 +136,8 @@ def main():
         return bench_net(args)
     if args.workload == "fermi":
         return bench_fermi(args)
+    if args.workload == "md":
+        return bench_md(args)
 
     import numpy as np
     import torch
@@ -517,6 +520,70 @@ def bench_net(args):
                      "peak": PEAK_FP16_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(f_fwd / (np.mean(fwd) * 1e-3) / 1e12 / PEAK_FP16_TFLOPS, 4), "traffic": None,
                      "kernel": "forward layers (split squaring kernel); the adjoint runs on the FP32 peak 157.3"},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_md(args):
+    """A molecular-dynamics-like sequence at N (default 8192, the small-gap stress spectrum):
+    between calls the eigenvalues move by up to 5 meV and the basis is rotated slightly.  The
+    first call runs Alg. 1; every later one runs the accelerated layers with the HOMO/LUMO
+    estimate from the previous call's history (sp2_estimate_gap).  Each call is timed."""
+    import numpy as np
+    import torch
+
+    from paper_2101_06385_amd import sp2, workloads
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    n_occ = n // 4
+    rng = np.random.default_rng(8000 + n)
+    eps = workloads.gapped_spectrum(rng, n, n_occ, -25.0, -12.55, -12.35, 25.0)
+    gen = None if args.gen_device == "cpu" else "cuda:0"
+    q = workloads.haar_orthogonal(rng, n, gen)
+    d = torch.empty((n, n), dtype=torch.float64, device=dev)
+    ws = sp2.alloc_workspace(sp2.workspace_size(n, sp2.options(args.precision, gap=(-1.0, 1.0))), dev)
+    calls = []
+    est = None
+    for step in range(args.steps + 1):
+        h = torch.from_numpy(workloads.symmetric_from_eigen(q, eps, gen)).to(dev)
+        if step == 0:   # warm the kernels up once, untimed
+            sp2.density(h, n_occ, precision=args.precision, out=d, workspace=ws)
+        inside = None if est is None else bool(eps[n_occ - 1] <= est[0] < est[1] <= eps[n_occ])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = sp2.density(h, n_occ, precision=args.precision, out=d, workspace=ws, gap=est)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        calls.append({"ms": round(ms, 3), "layers": info["layers"], "accelerated": info["accelerated"],
+                      "status": info["status_name"], "gap_violation": info["gap_violation"],
+                      "estimate_inside_gap": inside})
+        log("md step %d: %.2f ms, layers %d (%d accelerated), %s" % (step, ms, info["layers"], info["accelerated"],
+                                                                   info["status_name"]))
+        new = sp2.estimate_gap(info, n, args.precision)
+        if new is not None:
+            est = new
+        if step < args.steps:
+            eps = np.sort(eps + rng.uniform(-0.005, 0.005, n))
+            g = rng.standard_normal((n, n))
+            if gen is None:
+                qn, r = np.linalg.qr(q + 1e-3 * g)
+                q = qn * np.sign(np.diag(r))[None, :]
+            else:
+                qt, rt = torch.linalg.qr(torch.from_numpy(q + 1e-3 * g).to(gen))
+                q = (qt * torch.sign(torch.diagonal(rt))[None, :]).cpu().numpy()
+    acc = [c["ms"] for c in calls[1:]]
+    out = {
+        "metric": "time-to-D per call of a molecular-dynamics-like sequence at N=%d (first call Alg. 1, "
+                  "then accelerated layers from the previous call's HOMO/LUMO estimate)" % n,
+        "value": round(float(np.mean(acc)), 3), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": round(float(np.mean(acc)), 3), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f16" if args.precision == "fp16x2" else args.precision, "data": "synthetic",
+        "config": {"workload": "N=%d small-gap stress spectrum, 0.2 eV gap at 25%% occupation; per step eigenvalues "
+                               "move by U[-5,5] meV and the basis by QR(Q + 1e-3 G); Gershgorin bounds" % n,
+                   "precision": args.precision},
+        "plain_ms": calls[0]["ms"], "speedup_vs_plain": round(calls[0]["ms"] / float(np.mean(acc)), 3),
+        "calls": calls,
     }
     print(json.dumps(out), flush=True)
 

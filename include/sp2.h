@@ -316,6 +316,22 @@ int sp2_net_backward(const float* dGK, int ldg, int n, int K, const float* dW, c
                      void* stream);
 
 /*
+ * sp2_estimate_gap -- HOMO/LUMO estimates from the history of a converged call (host
+ * only; `info` as filled by sp2_density or sp2_density_batched for an n x n problem in
+ * `precision`), for the accelerated layers of a later call on a similar H (opt->homo/lumo).
+ * Near convergence IdErr is dominated by the LUMO image a and the HOMO deviation c; an
+ * ordinary layer maps (a, c) to (a^2, 2c - c^2) or (2a - a^2, c^2), so two consecutive IdErr
+ * values fix them, and the earlier layer maps (sigma_c, including accelerated ones) are
+ * inverted exactly.  Every pair of layers with IdErr <= 0.25 and the next IdErr above the
+ * rounding floor (1e-12 n in FP64, 1e-6 n otherwise) contributes; the highest HOMO and the
+ * lowest LUMO estimate are kept and the interval is narrowed by 10 % of its width.
+ * Estimates, not bounds: the accelerated call checks them (sp2_info.gap_violation).
+ * Returns SP2_OK, or SP2_EINVAL when the history holds no usable pair (for example an
+ * accelerated run whose last ordinary layers are at the rounding floor).
+ */
+int sp2_estimate_gap(const sp2_info* info, int n, int precision, double* homo, double* lumo);
+
+/*
  * Optimized finite-temperature expansion (Sec. "Optimized SP2 Finite Temperature
  * Fermi-Operator Expansion"): L layers of Eq. general SP2 on the rescaled spectrum
  * x in [0, 1] of H,

@@ -155,6 +155,8 @@ def lib() -> ctypes.CDLL:
                                    c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
     L.sp2_net_backward.restype = c_int
     pd = ctypes.POINTER(c_double)
+    L.sp2_estimate_gap.argtypes = [ctypes.POINTER(Info), c_int, c_int, pd, pd]
+    L.sp2_estimate_gap.restype = c_int
     L.sp2_fermi_fit.argtypes = [c_int, c_double, c_double, c_double, c_double, c_int, c_int, pd, pd, pd]
     L.sp2_fermi_fit.restype = c_int
     L.sp2_fermi_workspace_size.argtypes = [c_int, ctypes.POINTER(Options)]
@@ -572,3 +574,20 @@ def fermi_apply(h, theta, c, bounds, precision="fp16x2", tile=0, kernel=0, out=N
     if st != SP2_OK:
         raise SP2Error(st, "sp2_fermi_apply")
     return out, (tuple(obs[:]) if obs is not None else None)
+
+
+def estimate_gap(info: dict, n: int, precision="fp16x2"):
+    """(homo, lumo) estimated from the history of a converged call (see sp2_estimate_gap), or
+    None when the history holds no usable pair of layers."""
+    raw = Info()
+    raw.layers = int(info["layers"])
+    raw.emin, raw.emax = float(info["emin"]), float(info["emax"])
+    for i, v in enumerate(info["sigma_c"][:MAX_LAYERS]):
+        raw.sigma_c[i] = float(v)
+    for i, v in enumerate(info["iderr"][:MAX_LAYERS]):
+        raw.iderr[i] = float(v)
+    ho, lu = ctypes.c_double(), ctypes.c_double()
+    st = lib().sp2_estimate_gap(ctypes.byref(raw), int(n), _prec(precision), ctypes.byref(ho), ctypes.byref(lu))
+    if st != SP2_OK:
+        return None
+    return float(ho.value), float(lu.value)
