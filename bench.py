@@ -120,11 +120,12 @@ def main():
     ap.add_argument("--no-accel", action="store_true", help="skip the accelerated Deep-NN SP2 leg")
     ap.add_argument("--no-autotune", action="store_true", help="skip reporting the autotuner's choice")
     ap.add_argument("--gen-device", default="cuda", help="where the QR of the workload generator runs")
-    ap.add_argument("--workload", default="density", choices=["density", "batched", "net", "fermi", "md"],
+    ap.add_argument("--workload", default="density", choices=["density", "batched", "net", "fermi", "md", "sweep"],
                     help="density: the N=8192 headline (default); batched: 64 Hamiltonians of uneven "
                          "sizes in one graph; net: the 20-layer differentiable network at N=2048; fermi: "
                          "the 11-layer optimized finite-temperature expansion at N (default 8192); md: a "
-                         "sequence of slowly changing Hamiltonians with HOMO/LUMO estimates carried forward")
+                         "sequence of slowly changing Hamiltonians with HOMO/LUMO estimates carried forward; "
+                         "sweep: the headline measurement at N = 1024 .. 16384")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the SP2 path runs on one MI355X and is measured on one GPU; "
@@ -138,6 +139,8 @@ def main():
         return bench_fermi(args)
     if args.workload == "md":
         return bench_md(args)
+    if args.workload == "sweep":
+        return bench_sweep(args)
 
     import numpy as np
     import torch
@@ -521,6 +524,55 @@ def bench_net(args):
                      "frac": round(f_fwd / (np.mean(fwd) * 1e-3) / 1e12 / PEAK_FP16_TFLOPS, 4), "traffic": None,
                      "kernel": "forward layers (split squaring kernel); the adjoint runs on the FP32 peak 157.3"},
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_sweep(args):
+    """The headline measurement across sizes (the small-gap stress spectrum at each N):
+    layers, loop rate, squaring-kernel rate and time-to-D of FP16X2 Alg. 1 and of FP64 SP2."""
+    import numpy as np
+    import torch
+
+    from paper_2101_06385_amd import sp2, workloads
+
+    dev = torch.device("cuda:0")
+    gen = None if args.gen_device == "cpu" else "cuda:0"
+    rows = []
+    for n in (1024, 2048, 4096, 6144, 8192, 12288, 16384):
+        w = workloads.config3(n=n, device=gen)
+        h = torch.from_numpy(w.h).to(dev)
+        d = torch.empty_like(h)
+        ws = sp2.alloc_workspace(sp2.workspace_size(n, sp2.options(args.precision)), dev)
+        sp2.density(h, w.n_occ, precision=args.precision, out=d, workspace=ws)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, info, tm = sp2.density(h, w.n_occ, precision=args.precision, out=d, workspace=ws, timed=True)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        k = tm["squarings"]
+        f_layer = flop_split_layer(n)
+        sq = float(np.mean(tm["square_ms"][:k]))
+        row = {"n": n, "layers": info["layers"], "tile": info["tile"], "kernel": info["kernel"],
+               "time_to_d_ms": round(ms, 3), "loop_tflops": round(k * f_layer / (tm["loop_active_ms"] * 1e-3) / 1e12, 1),
+               "kernel_tflops": round(f_layer / (sq * 1e-3) / 1e12, 1),
+               "frac": round(f_layer / (sq * 1e-3) / 1e12 / PEAK_FP16_TFLOPS, 4),
+               "refine_ms": round(tm["refine_ms"], 3), "status": info["status_name"]}
+        if n <= 8192:
+            _, i64, t64 = sp2.density(h, w.n_occ, precision="fp64", timed=True)
+            row["fp64_time_to_d_ms"] = round(t64["total_ms"], 3)
+        rows.append(row)
+        log("sweep n=%d: %s" % (n, row))
+        del h, d, ws
+        torch.cuda.empty_cache()
+    big = [r for r in rows if r["n"] == 8192][0]
+    out = {"metric": "SP2 squaring-kernel TFLOP/s and time-to-D across N (FP16X2, small-gap stress spectrum)",
+           "value": big["kernel_tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": 3, "warmup": 1,
+           "ms_per_step": big["time_to_d_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f16" if args.precision == "fp16x2" else args.precision, "data": "synthetic",
+           "config": {"workload": "small-gap stress spectrum at N = 1024 .. 16384", "precision": args.precision},
+           "rows": rows}
     print(json.dumps(out), flush=True)
 
 

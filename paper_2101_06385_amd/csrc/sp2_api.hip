@@ -145,8 +145,9 @@ bool f64_sk_space(int np) { return ntiles_upper(np / 128) >= 64; }
 int auto_tile_main(int n, bool split) {
     // split modes: 256 tiles from n = 4096 (136 tiles; measured 690 vs 624 TFLOP/s for
     // 128 tiles there), persistent once there is a 256 tile per CU (n >= 6144); 128 tiles
-    // below 4096, 64 up to 256
-    if (split) return n <= 256 ? 64 : (n < 4096 ? 128 : 256);
+    // from 2048 to 4096; 64 tiles below 2048, where 128 tiles leave CUs idle (one layer at
+    // n = 1024: 0.034 vs 0.049 ms, n = 1536: 0.048 vs 0.064 ms; equal at 2048)
+    if (split) return n < 2048 ? 64 : (n < 4096 ? 128 : 256);
     return n <= 512 ? 64 : 128;
 }
 

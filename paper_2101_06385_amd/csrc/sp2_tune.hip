@@ -71,7 +71,7 @@ std::vector<Candidate> candidates(int n) {
     std::vector<Candidate> c;
     int dev = current_device(), cus = 256;
     if (dev >= 0) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (n <= 1024) c.push_back({64, 1});
+    if (n <= 2048) c.push_back({64, 1});
     for (int tile : {128, 256}) {
         if (tile == 256 && n <= 256) continue;
         c.push_back({tile, 1});

@@ -216,8 +216,10 @@ def test_async_call_and_query():
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x2"])
 def test_layers_after_the_stop_do_no_work(prec):
     """Synchronous calls enqueue up to two chunks of layers beyond the stopping layer; those
-    must return at once (skip flag) and leave S_{m-1} for the refinement untouched."""
-    w = wl.gapped(77, 1100, 300)
+    must return at once (skip flag) and leave S_{m-1} for the refinement untouched.  The size
+    keeps a working layer (about 80 us in FP16X2) well above the launch cost of a skipped
+    one (about 5 us)."""
+    w = wl.gapped(77, 2100, 600)
     h = torch.from_numpy(w.h).to(DEV)
     _, info, tm = sp2.density(h, w.n_occ, precision=prec, timed=True)
     m = info["layers"]
