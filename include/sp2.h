@@ -316,6 +316,19 @@ int sp2_net_backward(const float* dGK, int ldg, int n, int K, const float* dW, c
                      void* stream);
 
 /*
+ * sp2_observable -- FP64 reductions of a density matrix D and an observable A (Alg. 1's
+ * output Tr[D A]; with A = H the energy): out[0] = Tr D, out[1] = ||D||_F^2 and
+ * out[2] = sum_ij D_ij A_ij, which is Tr[D A] for symmetric D and A.  dD, dA: device FP64
+ * n x n (leading dimensions ldd, lda >= n); out: host, 3 doubles.  Fixed reduction order
+ * (bit-reproducible).  dWork: sp2_observable_workspace_size(n) bytes, 256-byte aligned.
+ * Synchronizes `stream`.  SP2_EINVAL, SP2_ENOMEM, SP2_EDEVICE, or SP2_ENONFINITE for a
+ * non-finite sum.
+ */
+size_t sp2_observable_workspace_size(int n);
+int sp2_observable(const double* dD, int ldd, const double* dA, int lda, int n, double* out, void* dWork,
+                   size_t work_bytes, void* stream);
+
+/*
  * sp2_estimate_gap -- HOMO/LUMO estimates from the history of a converged call (host
  * only; `info` as filled by sp2_density or sp2_density_batched for an n x n problem in
  * `precision`), for the accelerated layers of a later call on a similar H (opt->homo/lumo).

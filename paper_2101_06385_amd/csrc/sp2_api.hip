@@ -758,6 +758,27 @@ int sp2_spectral_bounds(const double* dH, int ldh, int n, double* emin, double* 
     return host.status;
 }
 
+size_t sp2_observable_workspace_size(int n) {
+    if (n <= 0 || n > 65536) return 0;
+    return align_up(sizeof(double) * 3 * dstats_blocks(n)) + align_up(sizeof(double) * 3);
+}
+
+int sp2_observable(const double* dD, int ldd, const double* dA, int lda, int n, double* out, void* dWork,
+                   size_t work_bytes, void* stream) {
+    if (n <= 0 || n > 65536 || ldd < n || lda < n || !dD || !dA || !out || !dWork) return SP2_EINVAL;
+    if (((uintptr_t)dWork) % kAlign) return SP2_EINVAL;
+    if (work_bytes < sp2_observable_workspace_size(n)) return SP2_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    double* parts = (double*)dWork;
+    double* sums = (double*)((char*)dWork + align_up(sizeof(double) * 3 * dstats_blocks(n)));
+    int nd = 0;
+    SP2_TRY(launch_dstats(dD, ldd, dA, lda, n, parts, &nd, s));
+    SP2_TRY(launch_sum3(parts, nd, sums, s));
+    SP2_TRY(hipMemcpyAsync(out, sums, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+    SP2_TRY(hipStreamSynchronize(s));
+    return (isfinite(out[0]) && isfinite(out[1]) && isfinite(out[2])) ? SP2_OK : SP2_ENONFINITE;
+}
+
 int sp2_square_padded(int n, int precision, int tile) {
     if (n <= 0) return 0;
     const bool split = precision == SP2_FP16X2 || precision == SP2_BF16X2;

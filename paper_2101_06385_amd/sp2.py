@@ -155,6 +155,10 @@ def lib() -> ctypes.CDLL:
                                    c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
     L.sp2_net_backward.restype = c_int
     pd = ctypes.POINTER(c_double)
+    L.sp2_observable_workspace_size.argtypes = [c_int]
+    L.sp2_observable_workspace_size.restype = c_size_t
+    L.sp2_observable.argtypes = [c_void_p, c_int, c_void_p, c_int, c_int, pd, c_void_p, c_size_t, c_void_p]
+    L.sp2_observable.restype = c_int
     L.sp2_estimate_gap.argtypes = [ctypes.POINTER(Info), c_int, c_int, pd, pd]
     L.sp2_estimate_gap.restype = c_int
     L.sp2_fermi_fit.argtypes = [c_int, c_double, c_double, c_double, c_double, c_int, c_int, pd, pd, pd]
@@ -591,3 +595,21 @@ def estimate_gap(info: dict, n: int, precision="fp16x2"):
     if st != SP2_OK:
         return None
     return float(ho.value), float(lu.value)
+
+
+def observable(d, a, stream=None):
+    """(Tr D, ||D||_F^2, sum_ij D_ij A_ij) for FP64 CUDA tensors D and A (see sp2_observable)."""
+    import torch
+
+    n = d.shape[0]
+    for t in (d, a):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.dim() == 2 and tuple(t.shape) == (n, n)
+                and t.stride(1) == 1):
+            raise TypeError("D and A must be square 2-D float64 CUDA tensors with unit column stride")
+    ws = alloc_workspace(int(lib().sp2_observable_workspace_size(n)), d.device)
+    out = (ctypes.c_double * 3)()
+    st = lib().sp2_observable(ctypes.c_void_p(d.data_ptr()), d.stride(0), ctypes.c_void_p(a.data_ptr()), a.stride(0),
+                              n, out, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(d.device, stream))
+    if st != SP2_OK:
+        raise SP2Error(st, "sp2_observable")
+    return tuple(out[:])

@@ -266,3 +266,24 @@ def test_stress_config_8192_fp64_sampled_rows():
     rows = [2, 5000]
     d = d.cpu().numpy()
     assert np.abs(d[rows] - dm.dm_rows(w.q, w.eps, w.n_occ, rows)).max() <= 1e-9
+
+
+def test_observable_reductions_against_fsum():
+    """sp2_observable: Tr D, ||D||_F^2 and sum_ij D_ij A_ij (Tr[D A] for a symmetric
+    observable A) against math.fsum of the same FP64 values, within the bound on any order
+    of FP64 additions; with A = H it is the energy sp2_density reports."""
+    import math
+
+    w = wl.gapped(88, 700, 200)
+    h = torch.from_numpy(w.h).to(DEV)
+    d, info = sp2.density(h, w.n_occ, want_energy=True)
+    rng = np.random.default_rng(89)
+    a = rng.standard_normal((700, 700))
+    a = 0.5 * (a + a.T)
+    dn = d.cpu().numpy()
+    for mat in (a, w.h):
+        out = sp2.observable(d, torch.from_numpy(mat).to(DEV))
+        terms = [np.diag(dn), (dn * dn).ravel(), (dn * mat).ravel()]
+        for got, t in zip(out, terms):
+            assert abs(got - math.fsum(t)) <= t.size * 2.0 ** -53 * math.fsum(np.abs(t)) + 1e-300
+    assert sp2.observable(d, h)[2] == info["energy"]
