@@ -140,3 +140,21 @@ def test_interval_inside_a_band_is_reported(prec):
         assert info["gap_violation"] > 0
         if prec == "fp64":
             assert info["gap_violation"] == ref.gap_violation
+
+
+def test_stress_config_16384_accelerated_sampled_rows():
+    """The second size of the stress case with its HOMO/LUMO values (persistent 4-wave
+    kernel): sampled rows against the exact projector and the oracle's accelerated
+    history on the eigenvalues."""
+    w = wl.config3(n=16384, device=DEV)
+    h = torch.from_numpy(w.h).to(DEV)
+    d, info = sp2.density(h, w.n_occ, gap=(w.homo, w.lumo))
+    assert info["status"] == sp2.SP2_OK and info["gap_violation"] == 0, info["status_name"]
+    rows = [5, 9000, 16383]
+    d = d.cpu().numpy()
+    assert np.abs(d[rows] - dm.dm_rows(w.q, w.eps, w.n_occ, rows)).max() <= 1e-3
+    assert np.array_equal(d[rows][:, :64], d[:64][:, rows].T)
+    e1, en = info["emin"], info["emax"]
+    lam0 = (en - w.eps) / (en - e1)
+    l0, h0 = osp2.homo_lumo_rescaled(w.homo, w.lumo, e1, en)
+    _check_accelerated_history(info, osp2.sp2_eigen_accelerated(lam0, w.n_occ, l0, h0))

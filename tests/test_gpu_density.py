@@ -287,3 +287,16 @@ def test_observable_reductions_against_fsum():
         for got, t in zip(out, terms):
             assert abs(got - math.fsum(t)) <= t.size * 2.0 ** -53 * math.fsum(np.abs(t)) + 1e-300
     assert sp2.observable(d, h)[2] == info["energy"]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("fp16x2", 1e-4), ("bf16x2", 1e-3)])
+def test_paper_10x10_case(prec, tol):
+    """The paper's 10 x 10 convergence example (H_ij uniform in [-1, 1], N_occ = 5) through
+    the C ABI against the eigendecomposition; in FP64 the sigma history is the oracle's."""
+    w = wl.small_random()
+    d, info = _run(w, precision=prec)
+    assert info["status"] == sp2.SP2_OK, info["status_name"]
+    assert np.abs(d - dm.dm_eigh(w.h, w.n_occ)).max() <= tol
+    if prec == "fp64":
+        ref = osp2.sp2_alg1(w.h, w.n_occ)
+        assert _same_early_history(info, ref, 1e-9) >= ref.layers - 4
