@@ -119,6 +119,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-accel", action="store_true", help="skip the accelerated Deep-NN SP2 leg")
     ap.add_argument("--no-autotune", action="store_true", help="skip reporting the autotuner's choice")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16X2 comparison leg")
     ap.add_argument("--gen-device", default="cuda", help="where the QR of the workload generator runs")
     ap.add_argument("--workload", default="density", choices=["density", "batched", "net", "fermi", "md", "sweep"],
                     help="density: the N=8192 headline (default); batched: 64 Hamiltonians of uneven "
@@ -256,6 +257,29 @@ def main():
     else:
         d64 = None
 
+    dbf = None
+    if args.precision == "fp16x2" and not args.no_bf16:
+        # the same solve with BF16 planes (the other split precision of the method)
+        dbf = torch.empty_like(h)
+        obf = sp2.options("bf16x2")
+        wsbf = sp2.alloc_workspace(sp2.workspace_size(n, obf), dev)
+        sp2.density(h, w.n_occ, precision="bf16x2", out=dbf, workspace=wsbf)      # warm
+        torch.cuda.synchronize()
+        bsteps = []
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            bsteps.append(sp2.density(h, w.n_occ, precision="bf16x2", out=dbf, workspace=wsbf, timed=True))
+        torch.cuda.synchronize()
+        ttdb = (time.perf_counter() - t1) * 1e3 / args.steps
+        _, ibf, _ = bsteps[-1]
+        sqb = [x for _, _, t in bsteps for x in t["square_ms"][:t["squarings"]]]
+        kb = f_layer / (float(np.mean(sqb)) * 1e-3) / 1e12
+        out["bf16x2"] = {"time_to_d_ms": round(ttdb, 3), "layers": ibf["layers"], "status": ibf["status_name"],
+                         "kernel_tflops": round(kb, 3), "frac": round(kb / PEAK_FP16_TFLOPS, 4),
+                         "trace_error": abs(ibf["trace"] - w.n_occ)}
+        log("bf16x2: time-to-D %.2f ms, layers %d, square kernel %.1f TFLOP/s" % (ttdb, ibf["layers"], kb))
+        del wsbf
+
     dacc = d64a = None
     if not args.no_accel:
         # Accelerated Deep-NN SP2 on the same H with its HOMO/LUMO values as the prior
@@ -323,6 +347,8 @@ def main():
         if d64 is not None:
             acc["fro_error_fp64"] = float(np.linalg.norm(d64.cpu().numpy() - d_ref))
         out["accuracy"] = acc
+        if dbf is not None:
+            out["bf16x2"]["fro_error"] = float(np.linalg.norm(dbf.cpu().numpy() - d_ref))
         if dacc is not None:
             out["accelerated"]["fro_error"] = float(np.linalg.norm(dacc.cpu().numpy() - d_ref))
             if "fp64" in out["accelerated"]:
