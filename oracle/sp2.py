@@ -43,7 +43,7 @@ STOP_FACTOR = 4.5
 
 
 # --------------------------------------------------------------------------------------
-# spectral bounds (the "spectral bound estimates" input of Alg. 1)
+# spectral bounds (the estimated spectral range that Alg. 1 takes as input)
 # --------------------------------------------------------------------------------------
 def gershgorin(h: np.ndarray):
     """Gershgorin interval [min_i(H_ii - r_i), max_i(H_ii + r_i)], r_i = sum_{j!=i}|H_ij|.
