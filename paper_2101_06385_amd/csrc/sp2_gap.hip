@@ -46,7 +46,6 @@ int sp2_estimate_gap(const sp2_info* info, int n, int precision, double* homo, d
     // layer j (1-based) applied to S_{j-1} gives S_j; history index j - 1
     for (int k = 0; k + 1 < m - 1; ++k) {
         const double s = info->sigma_c[k];
-        if (!(fabs(s) >= 1.0)) continue;
         if (fabs(s) != 1.0) continue;                     // the pair's layer must be an ordinary one
         const double e0 = info->iderr[k], e1 = info->iderr[k + 1];
         if (!(e0 <= kUpper) || !(e1 >= floor_abs)) continue;
