@@ -82,9 +82,9 @@ bool sk_wanted(bool split, int tile, int kernel) {
 
 // Persistent variant used when the caller leaves the choice open (index into the
 // per-tile variant table of the kernel), the fastest measured on MI355X: for 256 tiles
-// 8 waves with 32-half slices up to n_p = 12288 (871 TFLOP/s at 8192), 4 waves above
-// (844 TFLOP/s at 16384, where the 8-wave variant reached 803); for 128 tiles the
-// 64-half slices.
+// 8 waves with 32-half slices up to n_p = 12288 (one layer at 12288: 5.52 ms against
+// 5.75 ms for 4 waves), 4 waves above (16384: 14.69 ms against 15.41 ms for 8 waves);
+// for 128 tiles the 64-half slices.
 int sk_auto_variant(int tile, int np) {
     if (tile == 256) return np <= 12288 ? 3 : 2;
     return 1;
