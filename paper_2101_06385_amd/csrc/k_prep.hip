@@ -228,8 +228,8 @@ __device__ __forceinline__ void init_body(const double* __restrict__ h, int ldh,
             const float xs = (float)vs * in_scale;
             const T16 h0 = (T16)xs;
             const T16 h1 = (T16)(xs - (float)h0);
-            p0[(size_t)gi * np + gj] = h0;
-            p1[(size_t)gi * np + gj] = h1;
+            p0[(size_t)gi * plane_ld(np) + gj] = h0;
+            p1[(size_t)gi * plane_ld(np) + gj] = h1;
         }
         const double vd = (double)vs;
         if (gi == gj) tr += vd;
@@ -248,8 +248,9 @@ __device__ __forceinline__ void init_body(const double* __restrict__ h, int ldh,
                 const float xs = (float)vs * in_scale;
                 const T16 h0 = (T16)xs;
                 const T16 h1 = (T16)(xs - (float)h0);
-                p0[off] = h0;
-                p1[off] = h1;
+                const size_t poff = (size_t)(c0 + r) * plane_ld(np) + (r0 + c);
+                p0[poff] = h0;
+                p1[poff] = h1;
             }
         }
     }
@@ -517,13 +518,16 @@ __global__ __launch_bounds__(kThreads) void k_fill(double* __restrict__ d, int l
 
 template <typename T16>
 __global__ __launch_bounds__(kThreads) void k_split(const float* __restrict__ x, T16* __restrict__ p0,
-                                                    T16* __restrict__ p1, size_t total, float in_scale) {
+                                                    T16* __restrict__ p1, int np, float in_scale) {
+    // x: np x np (row stride np); planes: row stride plane_ld(np)
+    const size_t total = (size_t)np * np, pld = (size_t)plane_ld(np);
     for (size_t idx = (size_t)blockIdx.x * kThreads + threadIdx.x; idx < total;
          idx += (size_t)gridDim.x * kThreads) {
         const float xs = x[idx] * in_scale;
         const T16 h0 = (T16)xs;
-        p0[idx] = h0;
-        p1[idx] = (T16)(xs - (float)h0);
+        const size_t o = (idx / np) * pld + idx % np;
+        p0[o] = h0;
+        p1[o] = (T16)(xs - (float)h0);
     }
 }
 
@@ -827,10 +831,10 @@ hipError_t launch_split(const float* x, void* p0, void* p1, int np, int precisio
     const float sc = ldexpf(1.f, scale_log2);
     if (precision == SP2_FP16X2)
         hipLaunchKernelGGL((k_split<_Float16>), dim3(grid_for(total)), dim3(kThreads), 0, s, x, (_Float16*)p0,
-                           (_Float16*)p1, total, sc);
+                           (_Float16*)p1, np, sc);
     else if (precision == SP2_BF16X2)
         hipLaunchKernelGGL((k_split<__bf16>), dim3(grid_for(total)), dim3(kThreads), 0, s, x, (__bf16*)p0,
-                           (__bf16*)p1, total, sc);
+                           (__bf16*)p1, np, sc);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -118,8 +118,9 @@ __device__ __forceinline__ void split_body(const SquareArgs& a, int t) {
 
     const T16* x0 = (const T16*)a.x0;
     const T16* x1 = (const T16*)a.x1;
-    const T16* src[4] = {x0 + (size_t)I * BT * np, x1 + (size_t)I * BT * np, x0 + (size_t)J * BT * np,
-                         x1 + (size_t)J * BT * np};
+    const size_t pld = (size_t)plane_ld(np);   // plane row stride
+    const T16* src[4] = {x0 + (size_t)I * BT * pld, x1 + (size_t)I * BT * pld, x0 + (size_t)J * BT * pld,
+                         x1 + (size_t)J * BT * pld};
 
     u32x4 stg[4][CPT];
     f32x16 acc[MB][NB];
@@ -139,7 +140,7 @@ __device__ __forceinline__ void split_body(const SquareArgs& a, int t) {
             for (int i = 0; i < CPT; ++i) {
                 const int q = tid + i * NT;
                 const int r = q >> 2, c = q & 3;
-                stg[arr][i] = *(const u32x4*)(src[arr] + (size_t)r * np + k0 + c * 8);
+                stg[arr][i] = *(const u32x4*)(src[arr] + (size_t)r * pld + k0 + c * 8);
             }
     };
     auto lstore = [&](int buf) {
@@ -238,8 +239,9 @@ __device__ __forceinline__ void split_body(const SquareArgs& a, int t) {
                         const size_t off = (size_t)(row0 + e) * np + col;
                         so[off] = v[e];
                         if (p0) {
-                            p0[off] = h0[e];
-                            p1[off] = h1[e];
+                            const size_t poff = (size_t)(row0 + e) * pld + col;
+                            p0[poff] = h0[e];
+                            p1[poff] = h1[e];
                         }
                         fr += 2.0 * (double)v[e] * (double)v[e];
                     }
@@ -248,8 +250,9 @@ __device__ __forceinline__ void split_body(const SquareArgs& a, int t) {
                     if (p0) {
                         vec4 q0 = {h0[0], h0[1], h0[2], h0[3]};
                         vec4 q1 = {h1[0], h1[1], h1[2], h1[3]};
-                        *(vec4*)(p0 + moff) = q0;
-                        *(vec4*)(p1 + moff) = q1;
+                        const size_t pmoff = (size_t)col * pld + row0;
+                        *(vec4*)(p0 + pmoff) = q0;
+                        *(vec4*)(p1 + pmoff) = q1;
                     }
                 } else {
 #pragma unroll
@@ -259,15 +262,17 @@ __device__ __forceinline__ void split_body(const SquareArgs& a, int t) {
                         const size_t off = (size_t)row * np + col;
                         so[off] = v[e];
                         if (p0) {
-                            p0[off] = h0[e];
-                            p1[off] = h1[e];
+                            const size_t poff = (size_t)row * pld + col;
+                            p0[poff] = h0[e];
+                            p1[poff] = h1[e];
                         }
                         if (row < col) {
                             const size_t moff = (size_t)col * np + row;
                             so[moff] = v[e];
                             if (p0) {
-                                p0[moff] = h0[e];
-                                p1[moff] = h1[e];
+                                const size_t pmoff = (size_t)col * pld + row;
+                                p0[pmoff] = h0[e];
+                                p1[pmoff] = h1[e];
                             }
                             fr += 2.0 * (double)v[e] * (double)v[e];
                         } else {

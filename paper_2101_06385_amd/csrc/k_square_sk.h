@@ -221,8 +221,9 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
         const int nsl = ke - kb;   // slices of this work item
         int I, J;
         tile_of(t, a.T, 8, &I, &J);
-        const T16* src[4] = {x0 + (size_t)I * BT * np, x1 + (size_t)I * BT * np, x0 + (size_t)J * BT * np,
-                             x1 + (size_t)J * BT * np};
+        const size_t pld = (size_t)plane_ld(np);   // plane row stride
+        const T16* src[4] = {x0 + (size_t)I * BT * pld, x1 + (size_t)I * BT * pld, x0 + (size_t)J * BT * pld,
+                             x1 + (size_t)J * BT * pld};
 
         auto issue = [&](int buf, int ks) {
 #pragma unroll
@@ -231,7 +232,7 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
                 const int arr = j / C::BPR;
                 const int qd = j % C::BPR;
                 const int row = qd * C::RPB + lrow;
-                const T16* g = src[arr] + (size_t)row * np + ks * SK + ((lpc ^ swz<C::CPR>(row)) << 3);
+                const T16* g = src[arr] + (size_t)row * pld + ks * SK + ((lpc ^ swz<C::CPR>(row)) << 3);
                 dma16(g, __builtin_amdgcn_readfirstlane(
                              lds_addr(lds + buf * C::STAGE + arr * C::ARR + qd * 1024)));
             }
@@ -248,7 +249,7 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
             for (int i = 0; i < C::PFI; ++i) {
                 const int q = tid + i * C::NT;
                 const int arr = q / BT, row = q % BT;
-                touch4(src[arr] + (size_t)row * np + (kb + p) * SK, scratch);
+                touch4(src[arr] + (size_t)row * pld + (kb + p) * SK, scratch);
             }
         };
         // fragments of unit u (0 <= u < UPS) of the slice in buffer buf
@@ -358,7 +359,7 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
                             const int arr = j / C::BPR;
                             const int qd = j % C::BPR;
                             const int row = qd * C::RPB + lrow;
-                            const T16* g = src[arr] + (size_t)row * np + ks * SK + ((lpc ^ swz<C::CPR>(row)) << 3);
+                            const T16* g = src[arr] + (size_t)row * pld + ks * SK + ((lpc ^ swz<C::CPR>(row)) << 3);
                             dma16(g, __builtin_amdgcn_readfirstlane(
                                          lds_addr(lds + buf * C::STAGE + arr * C::ARR + qd * 1024)));
                         }
@@ -507,8 +508,9 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
                                 const size_t off = (size_t)(row0 + e) * np + col;
                                 so[off] = y4[e];
                                 if (p0) {
-                                    p0[off] = h0[e];
-                                    p1[off] = h1[e];
+                                    const size_t poff = (size_t)(row0 + e) * pld + col;
+                                    p0[poff] = h0[e];
+                                    p1[poff] = h1[e];
                                 }
                                 fr += 2.0 * (double)y4[e] * (double)y4[e];
                             }
@@ -529,15 +531,17 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
                                 const size_t off = (size_t)row * np + col;
                                 so[off] = y4[e];
                                 if (p0) {
-                                    p0[off] = h0[e];
-                                    p1[off] = h1[e];
+                                    const size_t poff = (size_t)row * pld + col;
+                                    p0[poff] = h0[e];
+                                    p1[poff] = h1[e];
                                 }
                                 if (row < col) {
                                     const size_t moff = (size_t)col * np + row;
                                     so[moff] = y4[e];
                                     if (p0) {
-                                        p0[moff] = h0[e];
-                                        p1[moff] = h1[e];
+                                        const size_t pmoff = (size_t)col * pld + row;
+                                        p0[pmoff] = h0[e];
+                                        p1[pmoff] = h1[e];
                                     }
                                     fr += 2.0 * (double)y4[e] * (double)y4[e];
                                 } else {
@@ -559,7 +563,7 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
                         if (p0) {
                             static_for<0, 2>([&](auto k) {
                                 const int c = 16 * k + (olane >> 2), q = olane & 3;
-                                const size_t goff = (mrow0 + c) * np + mcol0 + 8 * q;
+                                const size_t goff = (mrow0 + c) * pld + mcol0 + 8 * q;
                                 *(vec8*)(p0 + goff) = *(const vec8*)(th0 + c * TH + 8 * q);
                                 *(vec8*)(p1 + goff) = *(const vec8*)(th1 + c * TH + 8 * q);
                             });

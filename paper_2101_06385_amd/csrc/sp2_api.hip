@@ -195,7 +195,7 @@ void make_plan(int n, const Opts& o, Plan* p) {
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) {
             p->off_p[i][j] = off;
-            if (p->split) off = align_up(off + 2 * np2);
+            if (p->split) off = align_up(off + 2 * (size_t)p->np * plane_ld(p->np));
         }
     p->off_s64 = off;
     off = align_up(off + (o.refine ? 8 * np2 : 0));
@@ -797,7 +797,7 @@ size_t sp2_square_workspace_size(int n, int precision, int tile, int kernel) {
     size_t off = kAlign;                               // coefficients
     off = align_up(off + sizeof(double) * 2 * nt);     // partials
     off = align_up(off + sizeof(double) * 2);          // sums
-    if (split) off = align_up(off + 4 * (size_t)np * np);
+    if (split) off = align_up(off + 4 * (size_t)np * plane_ld(np));
     if (sk_wanted(split, t, kernel)) {
         off = align_up(off + square_sk_partial_bytes(t, np));
         off = align_up(off + sizeof(int) * kMaxSkGrid);
@@ -852,8 +852,8 @@ int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int ker
     a.in_scale = ldexpf(1.f, scale_log2);
     if (split) {
         void* p0 = ws + off;
-        void* p1 = ws + off + 2 * (size_t)np * np;
-        off = align_up(off + 4 * (size_t)np * np);
+        void* p1 = ws + off + 2 * (size_t)np * plane_ld(np);
+        off = align_up(off + 4 * (size_t)np * plane_ld(np));
         SP2_TRY(launch_split((const float*)dX, p0, p1, np, precision, scale_log2, s));
         a.x0 = p0;
         a.x1 = p1;

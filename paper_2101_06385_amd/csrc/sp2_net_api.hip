@@ -66,7 +66,7 @@ bool net_plan(int n, int K, int precision, int ckpt_every, NetPlan* p) {
     p->off_ping = off;
     off = align_up(off + 2 * m2);
     p->off_planes = off;
-    if (p->split) off = align_up(off + 4 * (size_t)p->np * p->np * 2);
+    if (p->split) off = align_up(off + 4 * (size_t)p->np * plane_ld(p->np) * 2);
     p->off_g = off;
     off = align_up(off + 2 * m2);
     p->off_xout = off;
@@ -104,7 +104,8 @@ NetBuffers carve(const NetPlan& p, void* dWork) {
     b.ping[1] = b.ping[0] + b.m;
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j)
-            b.planes[i][j] = p.split ? (void*)(ws + p.off_planes + (size_t)(2 * i + j) * b.m * 2) : nullptr;
+            b.planes[i][j] =
+                p.split ? (void*)(ws + p.off_planes + (size_t)(2 * i + j) * p.np * plane_ld(p.np) * 2) : nullptr;
     b.g[0] = (float*)(ws + p.off_g);
     b.g[1] = b.g[0] + b.m;
     b.xout = (float*)(ws + p.off_xout);
