@@ -82,13 +82,9 @@ bool sk_wanted(bool split, int tile, int kernel) {
 
 // Persistent variant used when the caller leaves the choice open (index into the
 // per-tile variant table of the kernel), the fastest measured on MI355X: for 256 tiles
-// 8 waves with 32-half slices up to n_p = 12288 (one layer at 12288: 5.52 ms against
-// 5.75 ms for 4 waves), 4 waves above (16384: 14.69 ms against 15.41 ms for 8 waves);
-// for 128 tiles the 64-half slices.
-int sk_auto_variant(int tile, int np) {
-    if (tile == 256) return np <= 12288 ? 3 : 2;
-    return 1;
-}
+// 8 waves with 32-half slices (one layer at n = 12288: 5.58 ms against 5.63 ms for 4
+// waves; 16384: 11.76 against 12.04 ms); for 128 tiles the 64-half slices.
+int sk_auto_variant(int tile) { return tile == 256 ? 3 : 1; }
 
 // Resolves the squaring schedule for this device; false = one workgroup per tile.
 bool sk_resolve(const Plan& p, StreamK* sk, int* variant) {
@@ -97,7 +93,7 @@ bool sk_resolve(const Plan& p, StreamK* sk, int* variant) {
     if (hipGetDevice(&dev) != hipSuccess) return false;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
     int per_cu = 0, T = 0, nt = 0;
-    *variant = p.kernel >= 2 ? p.kernel - 2 : sk_auto_variant(p.tile_main, p.np);
+    *variant = p.kernel >= 2 ? p.kernel - 2 : sk_auto_variant(p.tile_main);
     return square_sk_plan(p.tile_main, *variant, p.np, cus, &per_cu, sk, &T, &nt);
 }
 
