@@ -68,6 +68,17 @@ def test_defaults_and_strings():
     assert "gfx950" in sp2.version()
 
 
+def test_split_workspaces_hold_padded_planes():
+    # the half planes of an np x np matrix are stored with a row pitch of np + 64 halves
+    L = sp2.lib()
+    for n in (1000, 4096, 8192, 16384):
+        np_ = L.sp2_square_padded(n, sp2.FP16X2, 0)
+        assert np_ >= n
+        assert L.sp2_square_workspace_size(n, sp2.FP16X2, 0, 0) >= 4 * np_ * (np_ + 64)
+        full = sp2.workspace_size(n, sp2.options(precision="fp16x2"))
+        assert full >= np_ * np_ * (2 * 4 + 2 * 8) + 4 * 2 * np_ * (np_ + 64)
+
+
 def test_workspace_size_scales_with_n_and_precision():
     sizes = {}
     for p in ("fp64", "fp32", "fp16x2", "bf16x2"):
