@@ -176,6 +176,95 @@ def test_small_random_case_mixed_precision_and_refinement():
         assert np.linalg.norm(res.d - d_ref) < 1e-3
 
 
+# ----------------------------------------------------------------------------- Alg. 1: eps term and ties
+GOLDEN_RATIO_INV = (math.sqrt(5.0) - 1.0) / 2.0
+
+
+def _alternation_threshold(first_sign):
+    """Fixed point that separates the eigenvalues sent to 1 from those sent to 0 by the
+    alternating two-step maps: x -> 2x^2 - x^4 (x^2 first) repels from the root
+    (sqrt 5 - 1)/2 of x^3 - 2x + 1 = (x - 1)(x^2 + x - 1); the mirror map x -> (2x - x^2)^2
+    (2x - x^2 first) repels from 1 minus that root."""
+    return GOLDEN_RATIO_INV if first_sign > 0 else 1.0 - GOLDEN_RATIO_INV
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_large_eps_forces_alternation(seed):
+    """Alg. 1's sign rule subtracts sigma_{n-1} eps: with eps far above N (|v| <= 2N without
+    it) every layer from the second on must take the sign opposite to the previous one.  A
+    sign slip in the eps term would repeat the previous sign instead.  The alternating chain
+    then converges every eigenvalue of S_0 to 0 or 1 according to the repelling fixed point
+    of the two-step map, which fixes D without reference to the oracle's code."""
+    w = wl.gapped(300 + seed, 90, 20 + 10 * seed)
+    e1, en = sp2.gershgorin(w.h)
+    lam0 = (en - w.eps) / (en - e1)
+    for res in (sp2.sp2_alg1(w.h, w.n_occ, eps=1e9, bounds=(e1, en)), sp2.sp2_eigen(lam0, w.n_occ, eps=1e9)):
+        assert res.converged
+        assert all(res.sigma[i] == -res.sigma[i - 1] for i in range(1, res.layers)), res.sigma
+        # layer 1 has no eps term (sigma_0 = 0): its sign is the plain rule's
+        assert res.sigma[0] == sp2.sp2_eigen(lam0, w.n_occ).sigma[0]
+    thr = _alternation_threshold(res.sigma[0])
+    assert np.min(np.abs(lam0 - thr)) > 1e-3          # no eigenvalue sits on the threshold
+    mres = sp2.sp2_alg1(w.h, w.n_occ, eps=1e9, bounds=(e1, en))
+    keep = lam0 > thr
+    expect = (w.q[:, keep]) @ (w.q[:, keep]).T
+    assert np.abs(mres.d - expect).max() < 1e-9
+
+
+def test_eps_rule_equals_its_closed_form():
+    """With delta = N_S - N_occ and IdErr = N_S - N_X >= 0, |2N_S - N_X - N_occ| - |N_X - N_occ|
+    equals 2 sign(delta) min(|delta|, IdErr), so Alg. 1 picks sigma_n = Sign(2 sign(delta)
+    min(|delta|, IdErr) - sigma_{n-1} eps).  Every recorded sign of runs with several eps is
+    checked against that form, and eps must change some decisions (so the term is exercised)."""
+    changed = 0
+    for seed in range(8):
+        rng = np.random.default_rng(700 + seed)
+        n = 60
+        lam0 = rng.uniform(0, 1, size=n)
+        n_occ = int(rng.integers(5, n - 5))
+        for eps in (0.0, 1e-3, 0.05, 0.5, 3.0):
+            res = sp2.sp2_eigen(lam0, n_occ, eps=eps)
+            prev = 0
+            for i in range(res.layers):
+                delta = res.ns[i] - n_occ
+                ide = res.ns[i] - res.nx[i]
+                v = 2.0 * np.sign(delta) * min(abs(delta), ide) - prev * eps
+                want = 1 if v > 0 else (-1 if v < 0 else (-prev if prev else 1))
+                assert res.sigma[i] == want, (seed, eps, i)
+                if eps > 0 and (v > 0) != (v + prev * eps > 0) and v != 0:
+                    changed += 1
+                prev = res.sigma[i]
+    assert changed > 0
+
+
+def test_exact_tie_at_the_first_layer_takes_the_square():
+    """Sign(0) reading: with S_0's spectrum {1/4, 1/4, 3/4, 3/4} and N_occ = 2, Tr S_0 = N_occ
+    exactly, so v = 0 at layer 1 where sigma_0 = 0: the tie gives +1 (X^2).  Dyadic values
+    keep every trace exact.  The run still ends on the exact projector onto the 3/4 states."""
+    lam = np.array([0.25, 0.75, 0.25, 0.75])
+    h = np.diag(1.0 - lam)                           # exact bounds [0, 1]: S_0 = I - H
+    for res in (sp2.sp2_alg1(h, 2, bounds=(0.0, 1.0)), sp2.sp2_eigen(lam, 2)):
+        assert res.ns[0] == 2.0 and res.sigma[0] == 1
+        assert res.converged
+    res = sp2.sp2_alg1(h, 2, bounds=(0.0, 1.0))
+    assert np.abs(res.d - np.diag([0.0, 1.0, 0.0, 1.0])).max() < 1e-12
+
+
+def test_exact_tie_at_a_later_layer_reverses_the_sign():
+    """Sign(0) after a signed layer: S_0's spectrum {1, 3, 9, 14, 15}/16 with N_occ = 2 has
+    Tr S_0 = 2.625 (sigma_1 = +1) and Tr S_1 = (1 + 9 + 81 + 196 + 225)/256 = 2 exactly, so
+    v = 0 at layer 2 and the tie takes -sigma_1 = -1.  (Found by exhaustive search over
+    sixteenths; the gap between 9/16 and 14/16 makes D unique.)"""
+    lam = np.array([1, 3, 9, 14, 15]) / 16.0
+    assert Fraction(sum(Fraction(int(k) ** 2, 256) for k in [1, 3, 9, 14, 15])) == 2
+    h = np.diag(1.0 - lam)
+    for res in (sp2.sp2_alg1(h, 2, bounds=(0.0, 1.0)), sp2.sp2_eigen(lam, 2)):
+        assert res.sigma[0] == 1 and res.ns[1] == 2.0 and res.sigma[1] == -1
+        assert res.converged
+    res = sp2.sp2_alg1(h, 2, bounds=(0.0, 1.0))
+    assert np.abs(res.d - np.diag([0.0, 0.0, 0.0, 1.0, 1.0])).max() < 1e-12
+
+
 # ----------------------------------------------------------------------------- Alg. 2
 def test_round_bf16_brute_force():
     # values on and between bfloat16 grid points near 1 (spacing 2^-7)
