@@ -221,7 +221,9 @@ int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int ker
 
 /*
  * sp2_density_batched -- sp2_density for `batch` independent Hamiltonians of (possibly)
- * different sizes in one go.  All arrays are HOST arrays of length `batch`; dH[i], dD[i]
+ * different sizes in one go: the batching of many small matrix products that the paper
+ * (Sec. "Mixed Precision Fermi-operator expansion on tensor cores", its closing remark on
+ * small N) expects to carry the SP2 recursion's rate to small matrices.  All arrays are HOST arrays of length `batch`; dH[i], dD[i]
  * are device pointers as in sp2_density.  Options apply to every problem (precision
  * SP2_FP16X2, SP2_BF16X2 or SP2_FP32; caller bounds are not accepted: each problem gets
  * its own Gershgorin bounds).  Every step of the recursion is one launch covering the
@@ -238,7 +240,8 @@ int sp2_density_batched(int batch, const double* const* dH, const int* ldh, doub
                         size_t work_bytes, void* stream);
 
 /*
- * sp2_density_batched_gap -- sp2_density_batched with accelerated layers (Sec. Accelerated
+ * sp2_density_batched_gap -- sp2_density_batched (the batching of Sec. "Mixed Precision
+ * Fermi-operator expansion on tensor cores") with accelerated layers (Sec. Accelerated
  * Deep-NN SP2) for every problem: homo[i] < lumo[i] (host arrays, finite) is an interval
  * inside the HOMO-LUMO gap of H_i, as opt->homo/lumo of sp2_density with accelerate set;
  * opt->accelerate itself must be 0.  Each problem's result is the one sp2_density gives
@@ -297,7 +300,9 @@ void sp2_autotune_reset(void);
  *   dW, dB, dC  device FP32 arrays of K coefficients.
  *
  * sp2_net_forward writes X_K (n x n FP32, leading dimension ldk) and keeps the checkpoints
- * in dWork.  sp2_net_backward takes G_K = dL/dX_K (symmetric, FP32) and the SAME dWork,
+ * in dWork.  sp2_net_backward takes G_K = dL/dX_K (FP32, any n x n matrix: X_K is symmetric,
+ * so the library uses the symmetric part (G_K + G_K^T)/2, the gradient with respect to
+ * symmetric perturbations) and the SAME dWork,
  * n, K, precision and ckpt_every as the preceding forward call, and writes
  * dL/dW_k = <G_{k+1}, X_k^2>_F, dL/dB_k = <G_{k+1}, X_k>_F, dL/dc_k = Tr G_{k+1} into
  * ddW, ddB, ddC (device FP32, K each) and, if dG0 != NULL, G_0 = dL/dX_0, where

@@ -48,6 +48,28 @@ __global__ void k_copy_pad(const float* __restrict__ src, float* __restrict__ ds
     }
 }
 
+// dst (np x np, zero padding) <- (src + src^T)/2 for the n x n matrix src (leading dimension
+// ld): the part of a loss gradient that acts on a symmetric layer output.  One 32 x 32 output
+// tile per block; the mirrored input tile goes through LDS so that both reads are row
+// segments.  a + b == b + a in IEEE arithmetic, so the result is exactly symmetric.
+constexpr int kSymT = 32;
+__global__ __launch_bounds__(kThreads) void k_sym_pad(const float* __restrict__ src, float* __restrict__ dst,
+                                                      int n, int ld, int np) {
+    __shared__ float tr[kSymT][kSymT + 1];
+    const int bi = blockIdx.y * kSymT, bj = blockIdx.x * kSymT;
+    const int c = threadIdx.x % kSymT, r0 = threadIdx.x / kSymT;   // 8 rows per pass
+    for (int r = r0; r < kSymT; r += kThreads / kSymT) {
+        const int i = bj + r, j = bi + c;   // mirrored tile: rows of bj, columns of bi
+        tr[r][c] = (i < n && j < n) ? src[(size_t)i * ld + j] : 0.f;
+    }
+    __syncthreads();
+    for (int r = r0; r < kSymT; r += kThreads / kSymT) {
+        const int i = bi + r, j = bj + c;
+        const float a = (i < n && j < n) ? src[(size_t)i * ld + j] : 0.f;
+        dst[(size_t)i * np + j] = 0.5f * (a + tr[c][r]);
+    }
+}
+
 __device__ inline double wsum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
@@ -373,6 +395,13 @@ hipError_t launch_pack_coef(const float* w, const float* b, const float* c, int 
 hipError_t launch_copy_pad(const float* src, float* dst, int n, int ld, int np, int to_pad, hipStream_t s) {
     const size_t total = to_pad ? (size_t)np * np : (size_t)n * n;
     hipLaunchKernelGGL(k_copy_pad, dim3(grid_for(total)), dim3(kThreads), 0, s, src, dst, n, ld, np, to_pad);
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_pad(const float* src, float* dst, int n, int ld, int np, hipStream_t s) {
+    if (np % kSymT) return hipErrorInvalidValue;
+    const dim3 grid(np / kSymT, np / kSymT);
+    hipLaunchKernelGGL(k_sym_pad, grid, dim3(kThreads), 0, s, src, dst, n, ld, np);
     return hipGetLastError();
 }
 

@@ -80,7 +80,11 @@ __global__ void k_state_init(DevState* st, StateParams p) {
         st->first_sign = 0;
         st->refine_src = 0;
         st->ran = 0;
-        for (int i = 0; i < 3; ++i) st->coef[i] = 0.f;
+        for (int i = 0; i < 3; ++i) {
+            st->coef[i] = 0.f;
+            st->coef64[i] = 0.0;
+        }
+        st->pad3 = 0.0;
         for (int i = 0; i < 6; ++i) st->rcoef[i / 3][i % 3] = 0.f;
         st->pad1 = 0.f;
         st->eps = p.eps;
@@ -402,6 +406,9 @@ __device__ __forceinline__ void control_body(DevState* st, const double* __restr
             st->coef[0] = (float)ca;
             st->coef[1] = (float)cb;
             st->coef[2] = (float)cc;
+            st->coef64[0] = ca;
+            st->coef64[1] = cb;
+            st->coef64[2] = cc;
             st->skip = 0;
             st->layers = n;
             st->ran = n;

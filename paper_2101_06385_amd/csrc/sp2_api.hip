@@ -8,6 +8,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 using namespace sp2;
@@ -248,21 +249,69 @@ void fill_info(const DevState& st, const Plan* p, sp2_info* info) {
         if ((expr) != hipSuccess) return SP2_EDEVICE;   \
     } while (0)
 
-// Pinned, device-mapped int that the control kernel sets when Alg. 1 stops.
+// Pinned, device-mapped ints that the control kernel sets when Alg. 1 stops.  They are
+// allocated once per device and process (kFlagSlots slots of one 64-byte line each) and
+// never freed.  A synchronous call owns one slot from before its first launch until its
+// stream has drained, so no kernel of an earlier call can still write a slot that a later
+// call has reset.  With every slot taken the call runs without a flag (all layers enqueued,
+// as an asynchronous call does).
+constexpr int kFlagSlots = 64, kFlagDevices = 64, kFlagStride = 16;   // 16 ints = 64 bytes
+struct FlagPool {
+    std::mutex mu;
+    int* host[kFlagDevices] = {};
+    int* dev[kFlagDevices] = {};
+    unsigned long long used[kFlagDevices] = {};
+};
+FlagPool& flag_pool() {
+    static FlagPool pool;
+    return pool;
+}
+
 struct HostFlag {
     bool on = false, ok = true;
-    int* host = nullptr;
+    int device = -1, slot = -1;
+    volatile int* host = nullptr;
     int* dev = nullptr;
-    explicit HostFlag(bool enable) : on(enable) {
-        if (!on) return;
-        ok = hipHostMalloc((void**)&host, 64, hipHostMallocMapped) == hipSuccess;
-        if (ok) {
-            *host = 0;
-            ok = hipHostGetDevicePointer((void**)&dev, host, 0) == hipSuccess;
+    hipStream_t stream = nullptr;
+    HostFlag(bool enable, hipStream_t s) : stream(s) {
+        if (!enable) return;
+        if (hipGetDevice(&device) != hipSuccess || device < 0 || device >= kFlagDevices) return;
+        FlagPool& fp = flag_pool();
+        std::lock_guard<std::mutex> lock(fp.mu);
+        if (!fp.host[device]) {
+            int* h = nullptr;
+            int* d = nullptr;
+            if (hipHostMalloc((void**)&h, sizeof(int) * kFlagStride * kFlagSlots, hipHostMallocMapped) != hipSuccess) {
+                ok = false;
+                return;
+            }
+            if (hipHostGetDevicePointer((void**)&d, h, 0) != hipSuccess) {
+                (void)hipHostFree(h);
+                ok = false;
+                return;
+            }
+            fp.host[device] = h;
+            fp.dev[device] = d;
         }
+        for (int i = 0; i < kFlagSlots; ++i)
+            if (!((fp.used[device] >> i) & 1ull)) {
+                slot = i;
+                break;
+            }
+        if (slot < 0) return;
+        fp.used[device] |= 1ull << slot;
+        host = fp.host[device] + kFlagStride * slot;
+        dev = fp.dev[device] + kFlagStride * slot;
+        *host = 0;
+        on = true;
     }
     ~HostFlag() {
-        if (host) (void)hipHostFree(host);
+        if (slot < 0) return;
+        // a slot whose call's kernels may still be queued is never handed out again
+        if (hipStreamSynchronize(stream) != hipSuccess) return;
+        FlagPool& fp = flag_pool();
+        std::lock_guard<std::mutex> lock(fp.mu);
+        fp.used[device] &= ~(1ull << slot);
     }
 };
 
@@ -426,6 +475,10 @@ static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, in
     if (!ev.ok) return SP2_EDEVICE;
     SP2_TRY(ev.rec(ev.start, s));
 
+    // declared before any launch and destroyed after the final synchronization
+    HostFlag flag(info != nullptr || timing != nullptr, s);
+    if (!flag.ok) return SP2_EDEVICE;
+
     const DevState init = initial_state(n, n_occ, tol, o, p);
     SP2_TRY(launch_state_init(st, init, s));
 
@@ -467,6 +520,9 @@ static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, in
         memset(&a, 0, sizeof(a));
         a.parts = main_parts;
         a.coef = st->coef;
+        // FP64 layers take the unrounded coefficients (the accelerated layers' are not
+        // representable in FP32)
+        a.coef64 = o.precision == SP2_FP64 ? st->coef64 : nullptr;
         a.skip = &st->skip;
         a.np = p.np;
         a.ld_out = p.np;
@@ -481,8 +537,6 @@ static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, in
         // stops, so that no layers are enqueued long after convergence: layers go out in
         // chunks, two chunks ahead of the one the host waits for.  Asynchronous calls
         // enqueue every layer up to max_layers (later ones return at once).
-        HostFlag flag(info != nullptr || timing != nullptr);
-        if (!flag.ok) return SP2_EDEVICE;
         const int chunk = n >= 4096 ? 2 : (n >= 1024 ? 4 : 8);
         ChunkEvents cev(flag.on, (o.max_layers + chunk) / chunk + 1);
         if (!cev.ok) return SP2_EDEVICE;

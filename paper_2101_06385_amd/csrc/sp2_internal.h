@@ -45,6 +45,8 @@ struct DevState {
     double homo, lumo;  // caller's interval inside the gap (energies)
     double acc_l, acc_h;  // unoccupied eigenvalues of S_{n-1} in [0, acc_l], occupied in [acc_h, 1]
     double sigma_c[SP2_MAX_LAYERS + 1];
+    double coef64[3];   // the current layer's (alpha, beta, gamma) unrounded, for the FP64 layer kernels
+    double pad3;
 };
 
 // Upper-triangle tile enumeration shared by every kernel that works on (I <= J) tiles.
@@ -122,6 +124,8 @@ struct AdjointArgs {
 
 hipError_t launch_pack_coef(const float* w, const float* b, const float* c, int K, float* out, hipStream_t s);
 hipError_t launch_copy_pad(const float* src, float* dst, int n, int ld, int np, int to_pad, hipStream_t s);
+// dst (np x np, zero padded) <- (src + src^T)/2 of the n x n src (ld); np a multiple of 32
+hipError_t launch_sym_pad(const float* src, float* dst, int n, int ld, int np, hipStream_t s);
 int adjoint_grid(int tile, int np, int* T, int* ntiles, int* per);
 // adjoint variants 0..2 (k_net.hip): tile, schedule, split-K partial buffer, launch
 int adjoint_tile(int variant);

@@ -192,7 +192,8 @@ int sp2_net_backward(const float* dGK, int ldg, int n, int K, const float* dW, c
     // the backward uses the ones passed here
     SP2_TRY(launch_pack_coef(dW, dB, dC, K, b.coef, s));
     int gc = 0;
-    SP2_TRY(launch_copy_pad(dGK, b.g[gc], n, ldg, p.np, 1, s));
+    // X_K is symmetric, so only the symmetric part of G_K acts on it
+    SP2_TRY(launch_sym_pad(dGK, b.g[gc], n, ldg, p.np, s));
     StreamK sk;
     memset(&sk, 0, sizeof(sk));
     int dev = 0, cus = 0;

@@ -27,9 +27,8 @@ class SP2NetFunction(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gk):
         w, b, c = ctx.saved_tensors
-        # the loss gradient of a symmetric output is symmetrized before the adjoint
-        g = 0.5 * (gk + gk.transpose(0, 1))
-        dw, db, dc, g0 = sp2.net_backward(g.contiguous(), w, b, c, ctx.ws, ctx.precision, ctx.ckpt_every,
+        # sp2_net_backward takes the symmetric part of gk itself
+        dw, db, dc, g0 = sp2.net_backward(gk.contiguous(), w, b, c, ctx.ws, ctx.precision, ctx.ckpt_every,
                                           want_g0=ctx.needs_input_grad[0])
         return g0, dw, db, dc, None, None
 

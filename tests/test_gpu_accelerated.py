@@ -43,6 +43,13 @@ def test_fp64_accelerated_against_oracle(case):
     assert np.linalg.norm(d - dm.dm_construct(w.q, w.eps, w.n_occ)) < 1e-10
     assert abs(info["idem"]) < 1e-12
     _check_accelerated_history(info, ref)
+    # the accelerated layers run with their FP64 coefficients: the traces of every layer
+    # through the first ordinary one follow the oracle's to FP64 rounding (about 1e-15
+    # between two FP64 evaluations; FP32-rounded coefficients would show about 1e-8)
+    for i in range(ref.accelerated + 1):
+        assert abs(info["ns"][i] - ref.ns[i]) <= 1e-12 * max(1.0, abs(ref.ns[i])), (i, info["ns"][i], ref.ns[i])
+        assert abs(info["nx"][i] - ref.nx[i]) <= 1e-12 * max(1.0, abs(ref.nx[i])), (i, info["nx"][i], ref.nx[i])
+    assert np.abs(d - ref.d).max() <= 1e-12
     # Alg. 1 layers after the accelerated ones: same signs while IdErr is above the FP64 floor
     for i in range(ref.accelerated, ref.layers):
         if ref.iderr[i] < 1e-9:

@@ -73,6 +73,33 @@ def test_adjoint_matches_oracle_gradient(prec):
     assert np.abs(g0n - rg).max() <= tol * np.abs(rg).max()
 
 
+@pytest.mark.parametrize("prec,n", [("fp32", 256), ("fp16x2", 300)])
+def test_backward_takes_the_symmetric_part_of_a_general_gradient(prec, n):
+    """sp2_net_backward given a non-symmetric G_K (through the C ABI) returns the adjoint of
+    (G_K + G_K^T)/2, the gradient with respect to the symmetric output: against the FP64 matrix
+    adjoint started from that symmetric part, with a ragged edge at n = 300."""
+    k = 6
+    w, x0, wt, bt, ct, _ = _problem(n, k, 21 + n)
+    rng = np.random.default_rng(22 + n)
+    g = rng.standard_normal((n, n)).astype(np.float32)
+    xt, wtt, btt, ctt = _t(x0), _t(wt), _t(bt), _t(ct)
+    _, ws = sp2.net_forward(xt, wtt, btt, ctt, precision=prec)
+    dw, db, dc, g0 = sp2.net_backward(_t(g), wtt, btt, ctt, ws, precision=prec)
+    xs = onet.forward_matrix(x0.astype(np.float64), wt.astype(np.float64), bt.astype(np.float64),
+                             ct.astype(np.float64))
+    gsym = 0.5 * (g.astype(np.float64) + g.T.astype(np.float64))
+    # the oracle starts its adjoint from 2 (X_K - T); this T makes that start gsym
+    _, rw, rb, rc, rg = onet.loss_grad_matrix(x0.astype(np.float64), xs[-1] - 0.5 * gsym, wt.astype(np.float64),
+                                              bt.astype(np.float64), ct.astype(np.float64))
+    tol = 2e-4 if prec == "fp32" else 2e-3
+    for got, ref in ((dw, rw), (db, rb), (dc, rc)):
+        got = got.cpu().numpy().astype(np.float64)
+        assert np.abs(got - ref).max() <= tol * np.abs(ref).max(), (prec, got, ref)
+    g0n = g0.cpu().numpy().astype(np.float64)
+    assert np.abs(g0n - rg).max() <= tol * np.abs(rg).max()
+    assert np.array_equal(g0n, g0n.T)
+
+
 @pytest.mark.parametrize("prec,n,k", [("fp32", 700, 5), ("fp16x2", 900, 6)])
 def test_adjoint_128_tiles_matches_oracle_gradient(prec, n, k):
     """Sizes above 512 run the 128-tile adjoint and forward kernels (several tiles and a
