@@ -38,7 +38,8 @@ const SkVariant* sk_variant(int tile, int variant) {
 
 // Persistent schedule for a split square on n_p: G = CUs x workgroups per CU (a multiple
 // of 8, at most kMaxSkGrid), R whole rounds, and the leftover tiles cut into s = G / rem
-// K-chunks.  Returns false when there are fewer tiles than workgroups.
+// K-chunks.  With fewer tiles than workgroups the stream-K form splits all the K-slices of
+// all tiles evenly over the workgroups (see StreamK).
 bool square_sk_plan(int tile, int variant, int np, int cus, int* wg_per_cu, StreamK* sk, int* T, int* ntiles) {
     const SkVariant* V = sk_variant(tile, variant);
     if (!V) return false;
@@ -51,14 +52,27 @@ bool square_sk_plan(int tile, int variant, int np, int cus, int* wg_per_cu, Stre
     int g = cus * per_cu;
     if (g > kMaxSkGrid) g = kMaxSkGrid;
     g -= g % 8;
-    if (g < 8 || *ntiles < g) return false;
+    if (g < 8) return false;
     const int KS = np / V->sk;
     const int Q = V->sk >= 32 ? 1 : 2;   // tail chunks are cut on groups of Q slices
     sk->grid = g;
-    sk->rounds = *ntiles / g;
-    sk->tail_tiles = *ntiles % g;
-    sk->chunks = sk->tail_tiles ? g / sk->tail_tiles : 1;
-    if (sk->chunks > KS / Q) sk->chunks = KS / Q;
+    sk->stream_k = 0;
+    if (*ntiles < g) {
+        // fewer tiles than workgroups: stream-K ranges of equal length over all tiles
+        const long long ksq = KS / Q, U = (long long)*ntiles * ksq;
+        const long long per = U / g;   // whole units of the shortest range
+        if (per < 1 || 2 * g > kMaxSkGrid || *ntiles > kMaxSkGrid) return false;
+        if ((ksq + per - 1) / per + 1 > kSkMaxContrib) return false;
+        sk->rounds = 0;
+        sk->tail_tiles = *ntiles;
+        sk->chunks = 0;
+        sk->stream_k = Q;
+    } else {
+        sk->rounds = *ntiles / g;
+        sk->tail_tiles = *ntiles % g;
+        sk->chunks = sk->tail_tiles ? g / sk->tail_tiles : 1;
+        if (sk->chunks > KS / Q) sk->chunks = KS / Q;
+    }
     *wg_per_cu = per_cu;
     return true;
 }

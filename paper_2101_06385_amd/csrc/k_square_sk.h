@@ -170,6 +170,7 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
     typedef Cfg<T16, WM, WN, MB, NB, SK, ST, PF> C;
     __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS_ALL];
     __shared__ int s_flag;
+    __shared__ int s_slot[kSkMaxContrib];
     typedef typename H2<T16>::vec8 vec8;
     typedef typename H2<T16>::vec4 vec4;
     constexpr int BT = C::BT;
@@ -196,14 +197,41 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
     const T16* x1 = (const T16*)a.x1;
     const float alpha = a.coef[0], beta = a.coef[1], gamma = a.coef[2];
 
-    // work items: whole rounds, then at most one tail chunk
-    const int items = ONE_TILE ? 1 : sk.rounds + ((sk.tail_tiles > 0 && v < sk.tail_tiles * sk.chunks) ? 1 : 0);
+    // work items: whole rounds, then at most one tail chunk; or, in the stream-K form, the
+    // tiles that this workgroup's range of units [u0, u1) touches
+    const int SQ = ONE_TILE ? 0 : sk.stream_k;
+    const int ksq = SQ ? KS / SQ : 1;
+    const long long U = (long long)a.ntiles * ksq;
+    const int u0 = SQ ? (int)((long long)v * U / G) : 0;
+    const int u1 = SQ ? (int)((long long)(v + 1) * U / G) : 0;
+    const int first_tile = u0 / ksq;
+    int items;
+    if (ONE_TILE) items = 1;
+    else if (SQ) items = u1 > u0 ? (u1 - 1) / ksq - first_tile + 1 : 0;
+    else items = sk.rounds + ((sk.tail_tiles > 0 && v < sk.tail_tiles * sk.chunks) ? 1 : 0);
     for (int item = 0; item < items; ++item) {
         int t, kb, ke, chunk = -1, tail_tile = 0;
+        int slot = v;                  // partial tile slot of this work item
+        int contrib = sk.chunks;       // partials that make up the tile
         if (ONE_TILE) {
             t = t0;
             kb = 0;
             ke = KS;
+        } else if (SQ) {
+            t = first_tile + item;
+            const int lo = t * ksq, hi = lo + ksq;
+            const int a0 = u0 > lo ? u0 : lo, a1 = u1 < hi ? u1 : hi;
+            kb = SQ * (a0 - lo);
+            ke = SQ * (a1 - lo);
+            if (a0 > lo || a1 < hi) {
+                chunk = item == 0 ? 0 : 1;
+                slot = 2 * v + chunk;
+                tail_tile = t;
+                // ranges v' with u0(v') < hi and u1(v') > lo (every range is non-empty)
+                const int vf = (int)(((long long)(lo + 1) * G + U - 1) / U) - 1;
+                const int vl = (int)(((long long)hi * G + U - 1) / U) - 1;
+                contrib = vl - vf + 1;
+            }
         } else if (item < sk.rounds) {
             t = item * G + v;
             kb = 0;
@@ -429,7 +457,7 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
             constexpr size_t TILE_F = (size_t)BT * BT;
             // layout: per wave, per (m, n, quarter), 64 lanes x 4 floats; walked with one
             // running pointer so that no per-block addresses are kept live
-            f32x4* wp = (f32x4*)(sk.partial + (size_t)v * TILE_F + (size_t)owave * MB * NB * 16 * 64) + olane;
+            f32x4* wp = (f32x4*)(sk.partial + (size_t)slot * TILE_F + (size_t)owave * MB * NB * 16 * 64) + olane;
             static_for<0, MB>([&](auto m) {
                 static_for<0, NB>([&](auto n) {
                     static_for<0, 4>([&](auto q4) {
@@ -444,18 +472,30 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
             __syncthreads();
             if (tid == 0) s_flag = atomicAdd(sk.counter + tail_tile, 1);
             __syncthreads();
-            // each executed layer adds `chunks` arrivals per tail tile: the last one reduces
-            finish = ((s_flag + 1) % sk.chunks) == 0;
+            // each executed layer adds `contrib` arrivals per split tile: the last one reduces
+            finish = ((s_flag + 1) % contrib) == 0;
             if (finish) {
+                // stream-K: the partial slots of the contributors in K order (at most
+                // kSkMaxContrib by the plan); split tail: slots tail_tile * chunks + c
+                if (SQ && tid < contrib) {
+                    const int lo = t * ksq;
+                    const int vf = (int)(((long long)(lo + 1) * G + U - 1) / U) - 1;
+                    const int u = vf + tid;
+                    const int ut0 = (int)((long long)u * U / G) / ksq;
+                    s_slot[tid] = 2 * u + (ut0 == t ? 0 : 1);
+                }
                 __threadfence();
-                const f32x4* rp = (const f32x4*)(sk.partial + (size_t)tail_tile * sk.chunks * TILE_F +
-                                                 (size_t)owave * MB * NB * 16 * 64) + olane;
-                const size_t cstride = TILE_F / 4;   // f32x4 elements between chunks
+                __syncthreads();
+                auto slot_of = [&](int c) -> size_t {
+                    return SQ ? (size_t)s_slot[c] : (size_t)tail_tile * sk.chunks + c;
+                };
+                const f32x4* rp = (const f32x4*)(sk.partial + (size_t)owave * MB * NB * 16 * 64) + olane;
+                constexpr size_t cstride = TILE_F / 4;   // f32x4 elements per partial tile
                 static_for<0, MB>([&](auto m) {
                     static_for<0, NB>([&](auto n) {
                         static_for<0, 4>([&](auto q4) {
-                            f32x4 sum = rp[0];
-                            for (int c = 1; c < sk.chunks; ++c) sum += rp[c * cstride];
+                            f32x4 sum = rp[slot_of(0) * cstride];
+                            for (int c = 1; c < contrib; ++c) sum += rp[slot_of(c) * cstride];
                             static_for<0, 4>([&](auto e) { acc[m][n][4 * q4 + e] = sum[(int)e]; });
                             rp += 64;
                         });

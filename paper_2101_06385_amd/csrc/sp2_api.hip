@@ -457,9 +457,14 @@ static hipError_t run_trivial(const double* dH, int ldh, double* dD, int ldd, in
     return e;
 }
 
-static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ, double tol,
-                       const sp2_options* opt, sp2_info* info, void* dWork, size_t work_bytes, void* stream,
-                       sp2_timing* timing) {
+}  // extern "C"
+
+// The whole path of sp2_density.  poll_flag: a synchronous call may poll a mapped host flag
+// (allocated once per process) to stop enqueueing layers soon after Alg. 1 stops; without it
+// every layer up to max_layers is enqueued (later ones return at once).
+int sp2::density_call(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ, double tol,
+                      const sp2_options* opt, sp2_info* info, void* dWork, size_t work_bytes, void* stream,
+                      sp2_timing* timing, bool poll_flag) {
     Opts o;
     if (!read_opts(opt, &o)) return SP2_EINVAL;
     if (n <= 0 || ldh < n || ldd < n || n_occ < 0 || n_occ > n || !dH || !dD || !dWork) return SP2_EINVAL;
@@ -476,7 +481,7 @@ static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, in
     SP2_TRY(ev.rec(ev.start, s));
 
     // declared before any launch and destroyed after the final synchronization
-    HostFlag flag(info != nullptr || timing != nullptr, s);
+    HostFlag flag(poll_flag && (info != nullptr || timing != nullptr), s);
     if (!flag.ok) return SP2_EDEVICE;
 
     const DevState init = initial_state(n, n_occ, tol, o, p);
@@ -628,16 +633,18 @@ static int run_density(const double* dH, int ldh, double* dD, int ldd, int n, in
     return host.status;
 }
 
+extern "C" {
+
 int sp2_density(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ, double tol,
                 const sp2_options* opt, sp2_info* info, void* dWork, size_t work_bytes, void* stream) {
-    return run_density(dH, ldh, dD, ldd, n, n_occ, tol, opt, info, dWork, work_bytes, stream, nullptr);
+    return density_call(dH, ldh, dD, ldd, n, n_occ, tol, opt, info, dWork, work_bytes, stream, nullptr, true);
 }
 
 int sp2_density_timed(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ, double tol,
                       const sp2_options* opt, sp2_info* info, void* dWork, size_t work_bytes, void* stream,
                       sp2_timing* timing) {
     if (!timing) return SP2_EINVAL;
-    return run_density(dH, ldh, dD, ldd, n, n_occ, tol, opt, info, dWork, work_bytes, stream, timing);
+    return density_call(dH, ldh, dD, ldd, n, n_occ, tol, opt, info, dWork, work_bytes, stream, timing, true);
 }
 
 

@@ -43,11 +43,19 @@ constexpr int kMaxSkGrid = 1024;
 // n = 16384 measured 14.5 ms with pitch np and 12.0 ms with this one (no change at 8192).
 __host__ __device__ inline int plane_ld(int np) { return np + 64; }
 constexpr int kSkVariants = 6;
+// Stream-K form (split squaring, stream_k = Q > 0): the ntiles x (KS / Q) units of Q
+// K-slices, tile-major, are cut into G contiguous ranges, one per workgroup; a tile that
+// several ranges share is finished by the last of its contributors, which sums their FP32
+// partials in K order.  Workgroup v keeps its partials in slots 2v (first tile of its
+// range) and 2v + 1 (last tile); `counter` then counts arrivals per tile.
 struct StreamK {
-    int grid, rounds, tail_tiles, chunks;
-    float* partial;     // FP32 partial tiles (split squaring, adjoint)
-    int* counter;       // arrivals per tail tile, counted modulo chunks
-    double* fpartial;   // FP64 partial tiles (FP64 layer)
+    int grid = 0, rounds = 0, tail_tiles = 0, chunks = 0;
+    float* partial = nullptr;     // FP32 partial tiles (split squaring, adjoint)
+    int* counter = nullptr;       // arrivals per tail tile, counted modulo chunks
+    double* fpartial = nullptr;   // FP64 partial tiles (FP64 layer)
+    int stream_k = 0;             // slices per stream-K unit; 0: whole rounds + split tail
+    int pad = 0;
 };
+constexpr int kSkMaxContrib = 16;   // most stream-K ranges that may share one tile
 
 }  // namespace sp2

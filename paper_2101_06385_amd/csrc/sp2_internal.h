@@ -220,4 +220,10 @@ hipError_t launch_store_coefs64(double* dst, const double* vals, int count, hipS
 hipError_t launch_sum3(const double* parts, int nparts, double* out3, hipStream_t s);
 hipError_t launch_mark_trivial(DevState* st, hipStream_t s);
 
+// The whole sp2_density path (sp2_api.hip); poll_flag = false never touches host memory
+// beyond the final read-back of the state (no mapped flag).
+int density_call(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ, double tol,
+                 const sp2_options* opt, sp2_info* info, void* dWork, size_t work_bytes, void* stream,
+                 sp2_timing* timing, bool poll_flag);
+
 }  // namespace sp2

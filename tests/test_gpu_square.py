@@ -121,6 +121,61 @@ def test_persistent_schedules_sampled_rows(prec, tile, kernel, n):
         assert abs(sums[0] - tr) <= 1e-10 * max(1.0, abs(tr)) and abs(sums[1] - fr) <= 1e-10 * fr
 
 
+@pytest.mark.parametrize("prec,tile,kernel,n", [
+    ("fp16x2", 128, 5, 2048), ("fp16x2", 128, 4, 2048), ("fp16x2", 128, 5, 3000), ("bf16x2", 128, 5, 3000),
+    ("fp16x2", 256, 5, 4096), ("fp16x2", 256, 4, 3000), ("fp16x2", 128, 7, 1500),
+])
+def test_stream_k_schedules_sampled_rows(prec, tile, kernel, n):
+    """Fewer tiles than workgroups: the persistent kernel splits the K-slices of all tiles
+    evenly over the workgroups (stream-K), and the tiles shared by several ranges are summed
+    by their last contributor.  Sizes with several tiles per range, several ranges per tile
+    and ragged edges; sampled rows against the oracle's exact products of the same planes."""
+    fmt = "fp16" if prec == "fp16x2" else "bf16"
+    s = 12 if fmt == "fp16" else 0
+    rng = np.random.default_rng(n + 10 * kernel + tile)
+    a = rng.standard_normal((n, n)).astype(np.float32) / np.float32(np.sqrt(n))
+    x = (a + a.T) * np.float32(0.5)
+    rows = sorted({0, 1, 127, 128, 255, 256, n // 3, n // 2, n - 2, n - 1})
+    x0, x1 = osp2.split_planes(x, fmt, s)
+    a0, a1 = np.abs(x0.astype(np.float64)), np.abs(x1.astype(np.float64))
+    mag = (a0[rows] @ a0 + a0[rows] @ a1 + a1[rows] @ a0) * 2.0 ** (-2 * s)
+    ref = osp2.mixed_square_rows(x, rows, fmt, s)
+    xt = torch.from_numpy(x).to(DEV)
+    outs = []
+    for alpha, beta, gamma in COEFS:
+        y, sums = sp2.square(xt, alpha, beta, gamma, precision=prec, tile=tile, kernel=kernel)
+        assert torch.equal(y, y.T)
+        yr = y[rows].cpu().numpy().astype(np.float64)
+        want = alpha * ref + beta * x[rows].astype(np.float64) + gamma * np.eye(n)[rows]
+        bound = 2.0 * n * U32 * mag * abs(alpha) + 2.0 * U32 * (np.abs(alpha * ref) + abs(beta) * np.abs(x[rows])
+                                                               + abs(gamma))
+        err = np.abs(yr - want)
+        assert np.all(err <= bound + 1e-30), float((err / (bound + 1e-30)).max())
+        tr = float(torch.trace(y.double()))
+        fr = float((y.double() ** 2).sum())
+        assert abs(sums[0] - tr) <= 1e-10 * max(1.0, abs(tr)) and abs(sums[1] - fr) <= 1e-10 * fr
+        outs.append(y)
+    # the fixed summation order makes the result reproducible bit for bit
+    y2, _ = sp2.square(xt, *COEFS[-1], precision=prec, tile=tile, kernel=kernel)
+    assert torch.equal(outs[-1], y2)
+
+
+@pytest.mark.parametrize("n,tile,kernel", [(2048, 128, 5), (3000, 256, 5)])
+def test_stream_k_schedule_in_the_density_path(n, tile, kernel):
+    """The whole path with a stream-K squaring schedule reports it and reaches the exact
+    projector (accuracy bar of the mixed modes)."""
+    from oracle import dm
+
+    w = wl.gapped(41 + n, n, n // 4, occ_lo=-30.0, homo=-0.5, lumo=0.5, virt_hi=30.0)
+    d, info = sp2.density(torch.from_numpy(w.h).to(DEV), w.n_occ, tile=tile, kernel=kernel)
+    assert info["kernel"] == kernel and info["tile"] == tile
+    assert info["status"] == sp2.SP2_OK, info["status_name"]
+    d = d.cpu().numpy()
+    assert np.array_equal(d, d.T)
+    assert np.linalg.norm(d - dm.dm_construct(w.q, w.eps, w.n_occ)) <= 1e-3 * np.sqrt(n)
+    assert abs(info["trace"] - w.n_occ) <= 1e-6
+
+
 def test_persistent_schedule_deterministic():
     n = 6100
     rng = np.random.default_rng(1)
