@@ -5,9 +5,19 @@
 namespace sp2 {
 
 template <typename T16>
-hipError_t launch_sk_t(int tile, int variant, const SquareArgs& a, const StreamK& sk, hipStream_t s);
-extern template hipError_t launch_sk_t<_Float16>(int, int, const SquareArgs&, const StreamK&, hipStream_t);
-extern template hipError_t launch_sk_t<__bf16>(int, int, const SquareArgs&, const StreamK&, hipStream_t);
+hipError_t launch_sk256_t(int variant, const SquareArgs& a, const StreamK& sk, hipStream_t s);
+template <typename T16>
+hipError_t launch_sk128_t(int variant, const SquareArgs& a, const StreamK& sk, hipStream_t s);
+extern template hipError_t launch_sk256_t<_Float16>(int, const SquareArgs&, const StreamK&, hipStream_t);
+extern template hipError_t launch_sk256_t<__bf16>(int, const SquareArgs&, const StreamK&, hipStream_t);
+extern template hipError_t launch_sk128_t<_Float16>(int, const SquareArgs&, const StreamK&, hipStream_t);
+extern template hipError_t launch_sk128_t<__bf16>(int, const SquareArgs&, const StreamK&, hipStream_t);
+template <typename T16>
+hipError_t launch_sk_t(int tile, int variant, const SquareArgs& a, const StreamK& sk, hipStream_t s) {
+    if (tile == 256) return launch_sk256_t<T16>(variant, a, sk, s);
+    if (tile == 128) return launch_sk128_t<T16>(variant, a, sk, s);
+    return hipErrorInvalidValue;
+}
 template <typename T16>
 hipError_t launch_dp_t(int tile, int variant, const SquareArgs& a, const SquareArgs* descs, const int* offs,
                        int nprob, int blocks, hipStream_t s);

@@ -720,37 +720,37 @@ hipError_t launch_dp_t(int tile, int variant, const SquareArgs& a, const SquareA
     return hipGetLastError();
 }
 
-template <typename T16>
-hipError_t launch_sk_t(int tile, int variant, const SquareArgs& a, const StreamK& sk, hipStream_t s) {
+// Persistent launches per tile edge (instantiated in separate units so they compile in
+// parallel).  Variant tables: keep in step with kV256 / kV128 in k_square2.hip.
 #define SP2_L(WM, WN, MB, NB, SK, ST, PF)                                                            \
     hipLaunchKernelGGL((k_square_sk<T16, WM, WN, MB, NB, SK, ST, PF>), dim3(sk.grid), dim3(64 * WM * WN), 0, \
                        s, a, sk)
-    // variant tables: keep in step with kV256 / kV128 in k_square2.hip
-    if (tile == 256) {
-        switch (variant) {
-            case 0: SP2_L(2, 2, 4, 4, 16, 4, 0); break;
-            case 1: SP2_L(2, 4, 4, 2, 16, 4, 0); break;
-            case 2: SP2_L(2, 2, 4, 4, 32, 2, 0); break;
-            case 3: SP2_L(2, 4, 4, 2, 32, 2, 0); break;
-            case 4: SP2_L(2, 2, 4, 4, 32, 2, 4); break;
-            case 5: SP2_L(2, 4, 4, 2, 32, 2, 4); break;
-            default: return hipErrorInvalidValue;
-        }
-    } else if (tile == 128) {
-        switch (variant) {
-            case 0: SP2_L(2, 2, 2, 2, 32, 4, 0); break;
-            case 1: SP2_L(2, 2, 2, 2, 64, 2, 0); break;
-            case 2: SP2_L(2, 2, 2, 2, 16, 4, 0); break;
-            case 3: SP2_L(2, 2, 2, 2, 32, 2, 0); break;
-            case 4: SP2_L(2, 2, 2, 2, 64, 2, 2); break;
-            case 5: SP2_L(2, 2, 2, 2, 32, 2, 4); break;
-            default: return hipErrorInvalidValue;
-        }
-    } else {
-        return hipErrorInvalidValue;
+template <typename T16>
+hipError_t launch_sk256_t(int variant, const SquareArgs& a, const StreamK& sk, hipStream_t s) {
+    switch (variant) {
+        case 0: SP2_L(2, 2, 4, 4, 16, 4, 0); break;
+        case 1: SP2_L(2, 4, 4, 2, 16, 4, 0); break;
+        case 2: SP2_L(2, 2, 4, 4, 32, 2, 0); break;
+        case 3: SP2_L(2, 4, 4, 2, 32, 2, 0); break;
+        case 4: SP2_L(2, 2, 4, 4, 32, 2, 4); break;
+        case 5: SP2_L(2, 4, 4, 2, 32, 2, 4); break;
+        default: return hipErrorInvalidValue;
     }
-#undef SP2_L
     return hipGetLastError();
 }
+template <typename T16>
+hipError_t launch_sk128_t(int variant, const SquareArgs& a, const StreamK& sk, hipStream_t s) {
+    switch (variant) {
+        case 0: SP2_L(2, 2, 2, 2, 32, 4, 0); break;
+        case 1: SP2_L(2, 2, 2, 2, 64, 2, 0); break;
+        case 2: SP2_L(2, 2, 2, 2, 16, 4, 0); break;
+        case 3: SP2_L(2, 2, 2, 2, 32, 2, 0); break;
+        case 4: SP2_L(2, 2, 2, 2, 64, 2, 2); break;
+        case 5: SP2_L(2, 2, 2, 2, 32, 2, 4); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+#undef SP2_L
 
 }  // namespace sp2
