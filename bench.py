@@ -55,8 +55,9 @@ def flop_plain_layer(n):
 
 # Persistent-kernel variants (waves, K-slice halves, LDS stages, L2 prefetch distance) per
 # tile edge, in the order of the library's kernel option 2..7.
-SK_VARIANTS = {256: [(4, 16, 4, 0), (8, 16, 4, 0), (4, 32, 2, 0), (8, 32, 2, 0), (4, 32, 2, 4), (8, 32, 2, 4)],
-               128: [(4, 32, 4, 0), (4, 64, 2, 0), (4, 16, 4, 0), (4, 32, 2, 0), (4, 64, 2, 2), (4, 32, 2, 4)]}
+# (waves, K-slice halves, LDS stages, rolling fragment pipeline) per persistent variant
+SK_VARIANTS = {256: [(4, 16, 4, 0), (8, 16, 4, 0), (4, 32, 2, 0), (8, 32, 2, 0), (4, 32, 2, 1), (8, 32, 2, 1)],
+               128: [(4, 32, 4, 0), (4, 64, 2, 0), (4, 16, 4, 0), (4, 32, 2, 0), (4, 64, 2, 1), (4, 32, 2, 1)]}
 
 
 def kernel_name(precision, tile, kernel):
@@ -64,11 +65,11 @@ def kernel_name(precision, tile, kernel):
     if precision in ("fp16x2", "bf16x2"):
         t16 = "_Float16" if precision == "fp16x2" else "__bf16"
         if kernel >= 2:
-            waves, sk, st, pf = SK_VARIANTS[tile][kernel - 2]
+            waves, sk, st, rp = SK_VARIANTS[tile][kernel - 2]
             wn = waves // 2
             mb = tile // 64
             nb = tile // (32 * wn)
-            return "k_square_sk<%s, 2, %d, %d, %d, %d, %d, %d>" % (t16, wn, mb, nb, sk, st, pf)
+            return "k_square_sk<%s, 2, %d, %d, %d, %d, %d, %d>" % (t16, wn, mb, nb, sk, st, rp)
         if kernel == 1 and tile in (128, 256):
             return "k_square_dp<%s, 2, %d, %d, 2, 32, 2>" % (t16, 4 if tile == 256 else 2, tile // 64)
         return "k_square_split<%s, %d>" % (t16, tile)

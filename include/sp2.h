@@ -75,9 +75,10 @@ typedef struct {
                           tile (direct-to-LDS pipeline for tiles 128/256), 8 = one workgroup
                           per tile with register staging (every tile), 2..7 = persistent schedule (whole rounds of tiles, then the
                           leftover tiles split along K), kernel variant 0..5 for the tile,
-                          as (waves, K-slice halves, LDS stages, L2 prefetch distance):
-                            256: (4,16,4,0) (8,16,4,0) (4,32,2,0) (8,32,2,0) (4,32,2,4) (8,32,2,4)
-                            128: (4,32,4,0) (4,64,2,0) (4,16,4,0) (4,32,2,0) (4,64,2,2) (4,32,2,4)
+                          as (waves, K-slice halves, LDS stages, rolling fragment pipeline:
+                          one set of fragment registers refilled as the MFMAs free them):
+                            256: (4,16,4,0) (8,16,4,0) (4,32,2,0) (8,32,2,0) (4,32,2,1) (8,32,2,1)
+                            128: (4,32,4,0) (4,64,2,0) (4,16,4,0) (4,32,2,0) (4,64,2,1) (4,32,2,1)
                           Only split modes with tiles of 128/256 use these.  FP64 mode:
                           0 = automatic, 1 = register-staged kernel, 2 / 3 / 4 = direct-to-LDS
                           kernel (128 tiles) with (4 waves, 2 stages) / (4, 4) / (8, 4),

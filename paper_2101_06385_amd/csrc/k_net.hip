@@ -268,14 +268,15 @@ __global__ __launch_bounds__(256) void k_adjoint_dl(AdjointArgs a, StreamK sk) {
                         *wp = vv;
                         wp += 64;
                     }
-            __threadfence();
+            // release: this partial is in memory before the arrival is counted
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __syncthreads();
             if (tid == 0) s_flag = atomicAdd(sk.counter + tail_tile, 1);
             __syncthreads();
             // each layer adds `chunks` arrivals per tail tile: the last one reduces
             finish = ((s_flag + 1) % sk.chunks) == 0;
             if (finish) {
-                __threadfence();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // acquire: the other partials are visible
                 const f32x4v* rp = (const f32x4v*)(sk.partial + (size_t)tail_tile * sk.chunks * TILE_F) +
                                    (size_t)wave * NB * NB * 4 * 64 + lane;
                 const size_t cstride = TILE_F / 4;

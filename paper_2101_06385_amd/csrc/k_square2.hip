@@ -27,17 +27,17 @@ extern template hipError_t launch_dp_t<__bf16>(int, int, const SquareArgs&, cons
                                                hipStream_t);
 
 // Variants of the persistent kernel per tile edge: (waves, slice width in halves, LDS
-// stages, L2 prefetch distance in slices).
+// stages, rolling fragment pipeline).
 // Selected by index; the measured best is the automatic choice of the host driver.
 namespace {
 struct SkVariant {
-    int waves, sk, stages, prefetch;
+    int waves, sk, stages, rolling;
 };
 // keep in step with the launch table in k_square_sk.h
 constexpr SkVariant kV256[kSkVariants] = {{4, 16, 4, 0}, {8, 16, 4, 0}, {4, 32, 2, 0},
-                                          {8, 32, 2, 0}, {4, 32, 2, 4}, {8, 32, 2, 4}};
+                                          {8, 32, 2, 0}, {4, 32, 2, 1}, {8, 32, 2, 1}};
 constexpr SkVariant kV128[kSkVariants] = {{4, 32, 4, 0}, {4, 64, 2, 0}, {4, 16, 4, 0},
-                                          {4, 32, 2, 0}, {4, 64, 2, 2}, {4, 32, 2, 4}};
+                                          {4, 32, 2, 0}, {4, 64, 2, 1}, {4, 32, 2, 1}};
 const SkVariant* sk_variant(int tile, int variant) {
     if (variant < 0 || variant >= kSkVariants) return nullptr;
     if (tile == 256) return &kV256[variant];
@@ -55,7 +55,7 @@ bool square_sk_plan(int tile, int variant, int np, int cus, int* wg_per_cu, Stre
     if (!V) return false;
     *T = np / tile;
     *ntiles = ntiles_upper(*T);
-    const int lds = V->stages * 4 * tile * V->sk * 2 + (V->prefetch ? 256 : 0);
+    const int lds = V->stages * 4 * tile * V->sk * 2;
     int per_cu = (160 * 1024) / lds;
     if (tile == 256 || per_cu < 1) per_cu = 1;   // 256 tiles: the accumulators fill the register file
     if (per_cu > 2) per_cu = 2;

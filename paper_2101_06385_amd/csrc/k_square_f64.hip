@@ -192,13 +192,14 @@ __device__ __forceinline__ void f64_body(const SquareArgs& a, int t, int kb, int
                 *wp = acc[m][n];
                 wp += 64;
             }
-        __threadfence();
+        // release: this partial is in memory before the arrival is counted
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
         if (tid == 0) *s_flag = atomicAdd(sk.counter + tail_tile, 1);
         __syncthreads();
         // each executed layer adds `chunks` arrivals per tail tile: the last one reduces
         if (((*s_flag + 1) % sk.chunks) != 0) return;
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // acquire: the other partials are visible
         const f64x4* rp = (const f64x4*)(sk.fpartial + (size_t)tail_tile * sk.chunks * TILE_D) +
                           (size_t)wave * kMB * kNB * 64 + lane;
         const size_t cstride = TILE_D / 4;

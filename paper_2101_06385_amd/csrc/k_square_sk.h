@@ -114,15 +114,15 @@ typedef __attribute__((address_space(3))) unsigned char lds_byte;
 __device__ __forceinline__ unsigned lds_addr(const unsigned char* p) {
     return (unsigned)(uintptr_t)(const lds_byte*)p;
 }
-// L2 prefetch of one 128-byte line per lane: a 4-byte direct load into a scratch LDS word
-// that nothing reads (no VGPR is written, so no register can be clobbered late).
-__device__ __forceinline__ void touch4(const void* g, unsigned lds_base) {
+// The same with a wave-uniform base address in SGPRs and a 32-bit per-lane byte offset:
+// half the address data of the 64-bit form, and no per-load vector address arithmetic.
+__device__ __forceinline__ void dma16s(unsigned voff, const void* sbase, unsigned lds_base) {
     asm volatile(
-        "s_mov_b32 m0, %1\n\t"
+        "s_mov_b32 m0, %2\n\t"
         "s_nop 0\n\t"
-        "global_load_lds_dword %0, off"
+        "global_load_lds_dwordx4 %0, %1"
         :
-        : "v"(g), "s"(lds_base)
+        : "v"(voff), "s"(sbase), "s"(lds_base)
         : "memory", "m0");
 }
 __device__ __forceinline__ void dma16(const void* g, unsigned lds_base) {
@@ -135,7 +135,7 @@ __device__ __forceinline__ void dma16(const void* g, unsigned lds_base) {
         : "memory", "m0");
 }
 
-template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST, int PF>
+template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST, int RP>
 struct Cfg {
     static constexpr int NW = WM * WN;
     static constexpr int NT = 64 * NW;
@@ -153,9 +153,7 @@ struct Cfg {
     static constexpr int BPR = BT / RPB;           // 1 KB blocks per panel slice
     static constexpr int LPW = 4 * BPR / NW;       // direct-load instructions per wave per slice
     static_assert((4 * BPR) % NW == 0, "slice blocks must split evenly over waves");
-    static constexpr int LINE = SK >= 64 ? 1 : 64 / SK;   // slices per 128-byte line of a row
-    static constexpr int PFI = 4 * BT / NT;        // prefetch instructions per wave per line group
-    static constexpr int LDS_ALL = LDS + (PF ? 256 : 0);
+    static constexpr int LDS_ALL = LDS;
     static_assert(LDS_ALL <= 160 * 1024, "LDS budget");
     static_assert(LPW * (ST - 1) <= 48, "vmcnt range of wait_vm");
 };
@@ -165,11 +163,12 @@ struct Cfg {
 // schedule of workgroup v: whole rounds, then at most one split-K tail chunk.
 // (The LDS arrays are declared here, not passed in: a generic pointer to them cast back to
 // an LDS address made the compiler emit an illegal instruction.)
-template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST, int PF, bool ONE_TILE>
+template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST, int RP, bool ONE_TILE>
 __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, int v, int t0) {
-    typedef Cfg<T16, WM, WN, MB, NB, SK, ST, PF> C;
+    typedef Cfg<T16, WM, WN, MB, NB, SK, ST, RP> C;
     __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS_ALL];
     __shared__ int s_flag;
+    __shared__ int s_ticket;
     __shared__ int s_slot[kSkMaxContrib];
     typedef typename H2<T16>::vec8 vec8;
     typedef typename H2<T16>::vec4 vec4;
@@ -179,6 +178,7 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
     constexpr int UPS = C::UPS;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);   // the same, known to be wave-uniform
     const int wm = wave / WN, wn = wave % WN;
     const int np = a.np;
     const int KS = np / SK;    // K-slices per tile
@@ -197,8 +197,8 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
     const T16* x1 = (const T16*)a.x1;
     const float alpha = a.coef[0], beta = a.coef[1], gamma = a.coef[2];
 
-    // work items: whole rounds, then at most one tail chunk; or, in the stream-K form, the
-    // tiles that this workgroup's range of units [u0, u1) touches
+    // work items: whole rounds, then tail chunks taken from a queue until it is empty; or,
+    // in the stream-K form, the tiles that this workgroup's range of units [u0, u1) touches
     const int SQ = ONE_TILE ? 0 : sk.stream_k;
     const int ksq = SQ ? KS / SQ : 1;
     const long long U = (long long)a.ntiles * ksq;
@@ -208,7 +208,11 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
     int items;
     if (ONE_TILE) items = 1;
     else if (SQ) items = u1 > u0 ? (u1 - 1) / ksq - first_tile + 1 : 0;
-    else items = sk.rounds + ((sk.tail_tiles > 0 && v < sk.tail_tiles * sk.chunks) ? 1 : 0);
+    else items = sk.rounds + (sk.tail_tiles > 0 ? G : 0);   // the queue ends the tail items
+    // Tail queue: one ticket per tail chunk plus one final (empty) ticket per workgroup, so
+    // every executed launch draws exactly total + G tickets from a counter that is cleared
+    // once per call; the ticket modulo total + G is the chunk.
+    const int total = sk.tail_tiles * sk.chunks;
     for (int item = 0; item < items; ++item) {
         int t, kb, ke, chunk = -1, tail_tile = 0;
         int slot = v;                  // partial tile slot of this work item
@@ -237,8 +241,17 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
             kb = 0;
             ke = KS;
         } else {
-            tail_tile = v / sk.chunks;
-            chunk = v % sk.chunks;
+            // Workgroups that finish their rounds early take the chunks, in tile-major
+            // order; which workgroup computes a chunk does not change any result (the chunk
+            // fixes the K range and the partial slot, and the partials are summed in chunk
+            // order).
+            if (tid == 0) s_ticket = atomicAdd(sk.counter + kSkQueueSlot, 1);
+            __syncthreads();
+            const int q = s_ticket % (total + G);
+            if (q >= total) break;
+            tail_tile = q / sk.chunks;
+            chunk = q % sk.chunks;
+            slot = q;
             t = sk.rounds * G + tail_tile;
             // chunk bounds on groups of Q slices, Q = 2 / UPS: every work item then runs an
             // even number of MFMA units
@@ -253,33 +266,22 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
         const T16* src[4] = {x0 + (size_t)I * BT * pld, x1 + (size_t)I * BT * pld, x0 + (size_t)J * BT * pld,
                              x1 + (size_t)J * BT * pld};
 
-        auto issue = [&](int buf, int ks) {
-#pragma unroll
-            for (int i = 0; i < LPW; ++i) {
-                const int j = wave * LPW + i;
-                const int arr = j / C::BPR;
-                const int qd = j % C::BPR;
-                const int row = qd * C::RPB + lrow;
-                const T16* g = src[arr] + (size_t)row * pld + ks * SK + ((lpc ^ swz<C::CPR>(row)) << 3);
-                dma16(g, __builtin_amdgcn_readfirstlane(
-                             lds_addr(lds + buf * C::STAGE + arr * C::ARR + qd * 1024)));
-            }
+        // Direct load l of this wave's share of a slice: panel arr, 1 KB block qd; the
+        // lane's byte offset in the panel slice does not depend on the slice.
+        unsigned voff[LPW];
+        static_for<0, LPW>([&](auto l) {
+            const int j = wv * LPW + l;
+            const int row = (j % C::BPR) * C::RPB + lrow;
+            voff[l] = (unsigned)(row * pld * sizeof(T16)) + (unsigned)((lpc ^ swz<C::CPR>(row)) << 4);
+        });
+        // direct load l (0 <= l < LPW) of this wave's share of slice ks into buffer buf
+        auto dma_one = [&](auto l, int buf, int ks) {
+            const int j = wv * LPW + l;
+            const int arr = j / C::BPR, qd = j % C::BPR;
+            const unsigned char* base = (const unsigned char*)src[arr] + (size_t)ks * SK * sizeof(T16);
+            dma16s(voff[l], base, lds_addr(lds + buf * C::STAGE + arr * C::ARR + qd * 1024));
         };
-        // L2 prefetch of the 128-byte lines holding slice p (relative to kb) of the four
-        // panels, when p starts a line; returns the vector-memory instructions issued
-        auto pf_ops = [&](int p) -> int {
-            return (PF > 0 && p < nsl && (kb + p) % C::LINE == 0) ? C::PFI : 0;
-        };
-        auto prefetch = [&](int p) {
-            if (pf_ops(p) == 0) return;
-            const unsigned scratch = __builtin_amdgcn_readfirstlane(lds_addr(lds + C::LDS));
-#pragma unroll
-            for (int i = 0; i < C::PFI; ++i) {
-                const int q = tid + i * C::NT;
-                const int arr = q / BT, row = q % BT;
-                touch4(src[arr] + (size_t)row * pld + (kb + p) * SK, scratch);
-            }
-        };
+        auto issue = [&](int buf, int ks) { static_for<0, LPW>([&](auto l) { dma_one(l, buf, ks); }); };
         // fragments of unit u (0 <= u < UPS) of the slice in buffer buf
         auto frags = [&](int buf, int u, vec8 (&fa0)[MB], vec8 (&fa1)[MB], vec8 (&fb0)[NB], vec8 (&fb1)[NB]) {
             const int fchunk = ((2 * u + (lane >> 5)) ^ swz<C::CPR>(rsub)) << 4;
@@ -323,124 +325,201 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
 
         // ---------------------------------------------------------------- main loop
         // slice kb + j lives in LDS buffer j % ST.  Prologue: the first ST slices in
-        // flight, the first one landed and its first unit read into fragment set P.
-        // Slice q is issued (with the prefetch of slice q + PF right after it) among the
-        // MFMAs that follow arrive(q - ST + 1); the prologue issues slices 0 .. ST - 1.
-        // To wait for slice t, a wave allows the vector-memory instructions it issued
-        // after slice t to stay outstanding (they complete in order).
+        // flight and the first one landed.  Slice q >= ST is issued right after the barrier
+        // that frees buffer q % ST.  To wait for slice t, a wave allows the direct loads it
+        // issued after slice t to stay outstanding (they complete in order).
         wait_vm(0);   // nothing of the previous item may still count against vmcnt
         const int pro = nsl < ST ? nsl : ST;
-        for (int q = 0; q < pro; ++q) {
-            issue(q, kb + q);
-            prefetch(q + PF);
-        }
-        auto after = [&](int tslice, int last_issued) {
-            int c = pf_ops(tslice + PF);
-            for (int q = tslice + 1; q <= last_issued; ++q) c += LPW + pf_ops(q + PF);
-            return c;
-        };
-        wait_vm(after(0, pro - 1));   // the first slice has landed
+        for (int q = 0; q < pro; ++q) issue(q, kb + q);
+        wait_vm((pro - 1) * LPW);   // the first slice has landed
         __syncthreads();
-        vec8 pa0[MB], pa1[MB], pb0[NB], pb1[NB];   // fragments of even units
-        vec8 qa0[MB], qa1[MB], qb0[NB], qb1[NB];   // fragments of odd units
-        frags(0, 0, pa0, pa1, pb0, pb1);
-        // Make slice `next` readable (its loads landed, every wave past the barrier, so
-        // the buffer of slice next - 1, already read into registers, is free) and refill
-        // that buffer with slice next + ST - 1.  Invariant on entry: slices up to
-        // next + ST - 2 have been issued.  The caller then reads `next`'s fragments.
-        // Make slice `next` readable: its loads landed (the ones this wave issued; all
-        // later ones may stay in flight) and every wave is past the barrier, so the buffer
-        // of slice next - 1, already read into registers, is free.
-        auto arrive = [&](int next) {
-            const int last = (next + ST - 2 < nsl - 1) ? next + ST - 2 : nsl - 1;   // last slice issued
-            if constexpr (PF == 0) {
-                wait_vm((last - next) * LPW);
-            } else {
-                wait_vm(after(next, last));
-            }
-            __syncthreads();
-        };
-        // The MFMAs of one unit with the direct loads that refill the buffer freed by
-        // arrive(next) (slice next + ST - 1) spread between the X0 X0 and X0 X1 products, so
-        // that their address arithmetic and issue overlap the matrix cores (scheduling
-        // barriers keep the compiler from regrouping them), then `mid` (the fragment reads of
-        // the next unit: by then the X0 fragments of this unit and its X1 column fragments
-        // are dead, which keeps the register count down), then the X1 X0 products.  Last,
-        // the L2 prefetch of slice next + ST - 1 + PF.
-        auto mma_issue = [&](const vec8 (&fa0)[MB], const vec8 (&fa1)[MB], const vec8 (&fb0)[NB],
-                             const vec8 (&fb1)[NB], int next, auto&& mid) {
-            constexpr int NM = 2 * MB * NB;
-            const bool doit = next + ST - 1 < nsl;
-            const int buf = (next - 1) % ST, ks = kb + next + ST - 1;
-#pragma unroll
-            for (int i = 0; i < NM; ++i) {
-                const int m = (i / NB) % MB, n = i % NB;
-                acc[m][n] = H2<T16>::mfma(fa0[m], i < MB * NB ? fb0[n] : fb1[n], acc[m][n]);
-                // the loads l with ceil(l NM / LPW) == i go right after MFMA i
-                const int l0 = (i * LPW + NM - 1) / NM, l1 = ((i + 1) * LPW + NM - 1) / NM;
-                if (l1 > l0) {
-                    __builtin_amdgcn_sched_barrier(0);
-                    if (doit) {
-#pragma unroll
-                        for (int l = l0; l < l1; ++l) {
-                            const int j = wave * LPW + l;
-                            const int arr = j / C::BPR;
-                            const int qd = j % C::BPR;
-                            const int row = qd * C::RPB + lrow;
-                            const T16* g = src[arr] + (size_t)row * pld + ks * SK + ((lpc ^ swz<C::CPR>(row)) << 3);
-                            dma16(g, __builtin_amdgcn_readfirstlane(
-                                         lds_addr(lds + buf * C::STAGE + arr * C::ARR + qd * 1024)));
+        if constexpr (RP) {
+            // Rolling fragment pipeline.  One set of fragment registers: each register takes
+            // the next unit's fragment as soon as the last MFMA that reads it has been issued,
+            // so the LDS reads of unit u + 1 overlap the MFMAs of unit u without a second
+            // set.  Per unit the products go X0 X1 (B1 column-block major: B1[n] is free
+            // after its MB products), X0 X0 (row-block major: A0[m] free after its NB
+            // products), X1 X0 (A1[m] free likewise), then B0 is free.  Scheduling barriers
+            // pin that order.  At the last unit of a slice the barrier sits after the X0 X1
+            // products: the fragments of this slice are all in registers by then (an explicit
+            // lgkmcnt(0) waits for the last of them).  The loads that refill its buffer go out
+            // in two halves, one spread over the X0 X0 and X1 X0 products right after the
+            // barrier, the other over the first unit of the next slice: issued in one burst by
+            // every wave at once they queue up in the vector memory path and hold up the
+            // waves' next MFMAs.
+            static_assert(ST == 2 && UPS >= 2, "rolling pipeline: two LDS stages, two units per slice");
+            constexpr int LH = LPW / 2;
+            vec8 A0[MB], A1[MB], B0[NB], B1[NB];
+            const int ra = wm * C::WTM, rb = wn * C::WTN;
+            auto rd = [&](int buf, int u, int arr, int r0) -> vec8 {
+                const int fchunk = ((2 * u + (lane >> 5)) ^ swz<C::CPR>(rsub)) << 4;
+                return *(const vec8*)(lds + buf * C::STAGE + arr * C::ARR + (r0 + rsub) * ROW + fchunk);
+            };
+            static_for<0, MB>([&](auto m) {
+                A0[m] = rd(0, 0, 0, ra + 32 * m);
+                A1[m] = rd(0, 0, 1, ra + 32 * m);
+            });
+            static_for<0, NB>([&](auto n) {
+                B0[n] = rd(0, 0, 2, rb + 32 * n);
+                B1[n] = rd(0, 0, 3, rb + 32 * n);
+            });
+            // One unit on the fragments in registers.  NX: read the fragments of unit nu of
+            // the slice in buffer nbuf meanwhile.  SE: that unit starts the next slice, so a
+            // barrier comes first.  With dma, the direct loads [LB, LE) of slice dks go to
+            // buffer dbuf, spread evenly over the MFMAs that follow the barrier (SE) or over
+            // all of the unit's MFMAs.
+            auto unit = [&](auto se_, auto nx_, auto lb_, auto le_, int nbuf, int nu, bool dma, int dbuf, int dks) {
+                constexpr bool SE = decltype(se_)::value, NX = decltype(nx_)::value;
+                constexpr int LB = decltype(lb_)::value, LE = decltype(le_)::value;
+                constexpr int G = MB * NB;
+                constexpr int NS = SE ? 2 * G : 3 * G;   // MFMA slots that loads may follow
+                // the loads that go right after MFMA slot pos
+                auto dma_at = [&](auto pos_) {
+                    constexpr int pos = decltype(pos_)::value;
+                    constexpr int l0 = LB + (pos * (LE - LB) + NS - 1) / NS;
+                    constexpr int l1 = LB + ((pos + 1) * (LE - LB) + NS - 1) / NS;
+                    if constexpr (l1 > l0) {
+                        if (dma) {
+                            static_for<l0, l1>([&](auto l) { dma_one(l, dbuf, dks); });
                         }
+                        __builtin_amdgcn_sched_barrier(0);
                     }
+                };
+                static_for<0, NB>([&](auto n) {
+                    static_for<0, MB>([&](auto m) {
+                        acc[m][n] = H2<T16>::mfma(A0[m], B1[n], acc[m][n]);
+                        __builtin_amdgcn_sched_barrier(0);
+                        if constexpr (!SE) dma_at(std::integral_constant<int, n * MB + m>{});
+                    });
+                    if constexpr (NX && !SE) {
+                        B1[n] = rd(nbuf, nu, 3, rb + 32 * n);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                });
+                if constexpr (SE && NX) {
+                    wait_vm(0);   // this wave's loads of the next slice (the only ones in flight)
+                    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+                    __builtin_amdgcn_sched_barrier(0);
+                    static_for<0, NB>([&](auto n) { B1[n] = rd(nbuf, nu, 3, rb + 32 * n); });
                     __builtin_amdgcn_sched_barrier(0);
                 }
+                static_for<0, 2 * G>([&](auto i) {
+                    constexpr int g3 = i >= G ? 1 : 0;
+                    constexpr int m = (i % G) / NB, n = i % NB;
+                    if constexpr (g3) acc[m][n] = H2<T16>::mfma(A1[m], B0[n], acc[m][n]);
+                    else acc[m][n] = H2<T16>::mfma(A0[m], B0[n], acc[m][n]);
+                    __builtin_amdgcn_sched_barrier(0);
+                    dma_at(std::integral_constant<int, SE ? (int)i : G + (int)i>{});
+                    if constexpr (NX && n == NB - 1) {
+                        if constexpr (g3) A1[m] = rd(nbuf, nu, 1, ra + 32 * m);
+                        else A0[m] = rd(nbuf, nu, 0, ra + 32 * m);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                });
+                if constexpr (NX) {
+                    static_for<0, NB>([&](auto n) { B0[n] = rd(nbuf, nu, 2, rb + 32 * n); });
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            };
+            using T_ = std::true_type;
+            using F_ = std::false_type;
+            using I0 = std::integral_constant<int, 0>;
+            using IH = std::integral_constant<int, LH>;
+            using IL = std::integral_constant<int, LPW>;
+            // Slice sl: its first unit issues the second half of slice sl + 1 (the prologue
+            // issued slices 0 and 1 whole); its last unit, after the barrier that frees
+            // buffer sl & 1, the first half of slice sl + 2 into that buffer.
+            int sl = 0;
+            for (; sl + 1 < nsl; ++sl) {
+                const int buf = sl & 1;
+                unit(F_{}, T_{}, IH{}, IL{}, buf, 1, sl >= 1, buf ^ 1, kb + sl + 1);
+                static_for<1, UPS - 1>([&](auto j) { unit(F_{}, T_{}, I0{}, I0{}, buf, j + 1, false, 0, 0); });
+                unit(T_{}, T_{}, I0{}, IH{}, buf ^ 1, 0, sl + 2 < nsl, buf, kb + sl + 2);
             }
-            mid();
+            static_for<0, UPS - 1>([&](auto j) { unit(F_{}, T_{}, I0{}, I0{}, sl & 1, j + 1, false, 0, 0); });
+            unit(T_{}, F_{}, I0{}, I0{}, 0, 0, false, 0, 0);
+        } else {
+            // Two fragment sets (P, Q), double buffered per unit.
+            auto arrive = [&](int next) {
+                const int last = (next + ST - 2 < nsl - 1) ? next + ST - 2 : nsl - 1;   // last slice issued
+                wait_vm((last - next) * LPW);
+                __syncthreads();
+            };
+            vec8 pa0[MB], pa1[MB], pb0[NB], pb1[NB];   // fragments of even units
+            vec8 qa0[MB], qa1[MB], qb0[NB], qb1[NB];   // fragments of odd units
+            frags(0, 0, pa0, pa1, pb0, pb1);
+            // The MFMAs of one unit with the direct loads that refill the buffer freed by
+            // arrive(next) (slice next + ST - 1) spread between the X0 X0 and X0 X1 products, so
+            // that their address arithmetic and issue overlap the matrix cores (scheduling
+            // barriers keep the compiler from regrouping them), then `mid` (the fragment reads
+            // of the next unit: by then the X0 fragments of this unit and its X1 column
+            // fragments are dead, which keeps the register count down), then the X1 X0 products.
+            auto mma_issue = [&](const vec8 (&fa0)[MB], const vec8 (&fa1)[MB], const vec8 (&fb0)[NB],
+                                 const vec8 (&fb1)[NB], int next, auto&& mid) {
+                constexpr int NM = 2 * MB * NB;
+                const bool doit = next + ST - 1 < nsl;
+                const int buf = (next - 1) % ST, ks = kb + next + ST - 1;
 #pragma unroll
-            for (int m = 0; m < MB; ++m)
+                for (int i = 0; i < NM; ++i) {
+                    const int m = (i / NB) % MB, n = i % NB;
+                    acc[m][n] = H2<T16>::mfma(fa0[m], i < MB * NB ? fb0[n] : fb1[n], acc[m][n]);
+                    // the loads l with ceil(l NM / LPW) == i go right after MFMA i
+                    const int l0 = (i * LPW + NM - 1) / NM, l1 = ((i + 1) * LPW + NM - 1) / NM;
+                    if (l1 > l0) {
+                        __builtin_amdgcn_sched_barrier(0);
+                        if (doit) {
 #pragma unroll
-                for (int n = 0; n < NB; ++n) acc[m][n] = H2<T16>::mfma(fa1[m], fb0[n], acc[m][n]);
-            if (doit) prefetch(next + ST - 1 + PF);
-        };
-        // Units run in pairs (P, Q); unit w is unit w % UPS of slice w / UPS.  Each step
-        // reads the next unit's fragments while the matrix cores work on the current one.
-        // The unit count is even; the last pair is peeled so that the loop body has no
-        // branch and the LDS-read waits stay exact.
-        const int nu = nsl * UPS;
-        int w = 0;
-        for (; w + 2 < nu; w += 2) {
+                            for (int l = l0; l < l1; ++l) dma_one(l, buf, ks);
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+                mid();
+#pragma unroll
+                for (int m = 0; m < MB; ++m)
+#pragma unroll
+                    for (int n = 0; n < NB; ++n) acc[m][n] = H2<T16>::mfma(fa1[m], fb0[n], acc[m][n]);
+            };
+            // Units run in pairs (P, Q); unit w is unit w % UPS of slice w / UPS.  Each step
+            // reads the next unit's fragments while the matrix cores work on the current one.
+            // The unit count is even; the last pair is peeled so that the loop body has no
+            // branch and the LDS-read waits stay exact.
+            const int nu = nsl * UPS;
+            int w = 0;
+            for (; w + 2 < nu; w += 2) {
+                if constexpr (UPS == 1) {
+                    arrive(w + 1);
+                    mma_issue(pa0, pa1, pb0, pb1, w + 1, [&] { frags((w + 1) % ST, 0, qa0, qa1, qb0, qb1); });
+                    arrive(w + 2);
+                    mma_issue(qa0, qa1, qb0, qb1, w + 2, [&] { frags((w + 2) % ST, 0, pa0, pa1, pb0, pb1); });
+                } else if constexpr (UPS == 2) {
+                    frags((w / 2) % ST, 1, qa0, qa1, qb0, qb1);
+                    mma(pa0, pa1, pb0, pb1);
+                    arrive((w + 2) / 2);
+                    mma_issue(qa0, qa1, qb0, qb1, (w + 2) / 2,
+                              [&] { frags(((w + 2) / 2) % ST, 0, pa0, pa1, pb0, pb1); });
+                } else {
+                    frags((w / UPS) % ST, (w + 1) % UPS, qa0, qa1, qb0, qb1);
+                    mma(pa0, pa1, pb0, pb1);
+                    if ((w + 2) % UPS == 0) {
+                        arrive((w + 2) / UPS);
+                        mma_issue(qa0, qa1, qb0, qb1, (w + 2) / UPS,
+                                  [&] { frags(((w + 2) / UPS) % ST, 0, pa0, pa1, pb0, pb1); });
+                    } else {
+                        frags(((w + 2) / UPS) % ST, (w + 2) % UPS, pa0, pa1, pb0, pb1);
+                        mma(qa0, qa1, qb0, qb1);
+                    }
+                }
+            }
             if constexpr (UPS == 1) {
                 arrive(w + 1);
-                mma_issue(pa0, pa1, pb0, pb1, w + 1, [&] { frags((w + 1) % ST, 0, qa0, qa1, qb0, qb1); });
-                arrive(w + 2);
-                mma_issue(qa0, qa1, qb0, qb1, w + 2, [&] { frags((w + 2) % ST, 0, pa0, pa1, pb0, pb1); });
-            } else if constexpr (UPS == 2) {
-                frags((w / 2) % ST, 1, qa0, qa1, qb0, qb1);
-                mma(pa0, pa1, pb0, pb1);
-                arrive((w + 2) / 2);
-                mma_issue(qa0, qa1, qb0, qb1, (w + 2) / 2,
-                          [&] { frags(((w + 2) / 2) % ST, 0, pa0, pa1, pb0, pb1); });
+                frags((w + 1) % ST, 0, qa0, qa1, qb0, qb1);
             } else {
                 frags((w / UPS) % ST, (w + 1) % UPS, qa0, qa1, qb0, qb1);
-                mma(pa0, pa1, pb0, pb1);
-                if ((w + 2) % UPS == 0) {
-                    arrive((w + 2) / UPS);
-                    mma_issue(qa0, qa1, qb0, qb1, (w + 2) / UPS,
-                              [&] { frags(((w + 2) / UPS) % ST, 0, pa0, pa1, pb0, pb1); });
-                } else {
-                    frags(((w + 2) / UPS) % ST, (w + 2) % UPS, pa0, pa1, pb0, pb1);
-                    mma(qa0, qa1, qb0, qb1);
-                }
             }
+            mma(pa0, pa1, pb0, pb1);
+            mma(qa0, qa1, qb0, qb1);
         }
-        if constexpr (UPS == 1) {
-            arrive(w + 1);
-            frags((w + 1) % ST, 0, qa0, qa1, qb0, qb1);
-        } else {
-            frags((w / UPS) % ST, (w + 1) % UPS, qa0, qa1, qb0, qb1);
-        }
-        mma(pa0, pa1, pb0, pb1);
-        mma(qa0, qa1, qb0, qb1);
         __syncthreads();   // all fragment reads done before LDS is reused below
 
         // Per-lane index arithmetic below is recomputed from an opaque copy of the thread
@@ -468,7 +547,8 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
                     });
                 });
             });
-            __threadfence();
+            // release: this partial is in memory before the arrival is counted
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __syncthreads();
             if (tid == 0) s_flag = atomicAdd(sk.counter + tail_tile, 1);
             __syncthreads();
@@ -484,23 +564,42 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
                     const int ut0 = (int)((long long)u * U / G) / ksq;
                     s_slot[tid] = 2 * u + (ut0 == t ? 0 : 1);
                 }
-                __threadfence();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // acquire: the other partials are visible
                 __syncthreads();
                 auto slot_of = [&](int c) -> size_t {
                     return SQ ? (size_t)s_slot[c] : (size_t)tail_tile * sk.chunks + c;
                 };
-                const f32x4* rp = (const f32x4*)(sk.partial + (size_t)owave * MB * NB * 16 * 64) + olane;
+                // acc = ((p_0 + p_1) + p_2) + ... in chunk order, one partial at a time: the
+                // loads of a partial are independent and go out in batches of RB row blocks
+                // (as many as the registers freed by the main loop hold)
+                const f32x4* rp0 = (const f32x4*)(sk.partial + (size_t)owave * MB * NB * 16 * 64) + olane;
                 constexpr size_t cstride = TILE_F / 4;   // f32x4 elements per partial tile
-                static_for<0, MB>([&](auto m) {
-                    static_for<0, NB>([&](auto n) {
-                        static_for<0, 4>([&](auto q4) {
-                            f32x4 sum = rp[slot_of(0) * cstride];
-                            for (int c = 1; c < contrib; ++c) sum += rp[slot_of(c) * cstride];
-                            static_for<0, 4>([&](auto e) { acc[m][n][4 * q4 + e] = sum[(int)e]; });
-                            rp += 64;
+                constexpr int RB = MB * NB >= 16 ? 1 : (MB >= 2 ? 2 : 1);
+                for (int c = 0; c < contrib; ++c) {
+                    const f32x4* rp = rp0 + slot_of(c) * cstride;
+                    static_for<0, MB / RB>([&](auto mb) {
+                        f32x4 pv[RB][NB][4];
+                        static_for<0, RB>([&](auto r) {
+                            static_for<0, NB>([&](auto n) {
+                                static_for<0, 4>([&](auto q4) {
+                                    pv[r][n][q4] = rp[(((mb * RB + r) * NB + n) * 4 + q4) * 64];
+                                });
+                            });
                         });
+                        static_for<0, RB>([&](auto r) {
+                            static_for<0, NB>([&](auto n) {
+                                static_for<0, 4>([&](auto q4) {
+                                    static_for<0, 4>([&](auto e) {
+                                        const float d = acc[mb * RB + r][n][4 * q4 + e];
+                                        acc[mb * RB + r][n][4 * q4 + e] = c == 0 ? pv[r][n][q4][(int)e]
+                                                                                : d + pv[r][n][q4][(int)e];
+                                    });
+                                });
+                            });
+                        });
+                        __builtin_amdgcn_sched_barrier(0);
                     });
-                });
+                }
             }
         }
 
@@ -637,12 +736,12 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
     }
 }
 
-template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST, int PF>
+template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST, int RP>
 __global__ __launch_bounds__(64 * WM * WN) void k_square_sk(SquareArgs a, StreamK sk) {
     if (a.skip && *a.skip) return;
     // XCD-aware order: the workgroups of one XCD get consecutive virtual indices
     const int v = (blockIdx.x & 7) * (sk.grid >> 3) + (blockIdx.x >> 3);
-    sk_body<T16, WM, WN, MB, NB, SK, ST, PF, false>(a, sk, v, 0);
+    sk_body<T16, WM, WN, MB, NB, SK, ST, RP, false>(a, sk, v, 0);
 }
 
 // One workgroup per upper-triangle tile of one problem, XCD-aware tile order.
@@ -722,8 +821,8 @@ hipError_t launch_dp_t(int tile, int variant, const SquareArgs& a, const SquareA
 
 // Persistent launches per tile edge (instantiated in separate units so they compile in
 // parallel).  Variant tables: keep in step with kV256 / kV128 in k_square2.hip.
-#define SP2_L(WM, WN, MB, NB, SK, ST, PF)                                                            \
-    hipLaunchKernelGGL((k_square_sk<T16, WM, WN, MB, NB, SK, ST, PF>), dim3(sk.grid), dim3(64 * WM * WN), 0, \
+#define SP2_L(WM, WN, MB, NB, SK, ST, RP)                                                            \
+    hipLaunchKernelGGL((k_square_sk<T16, WM, WN, MB, NB, SK, ST, RP>), dim3(sk.grid), dim3(64 * WM * WN), 0, \
                        s, a, sk)
 template <typename T16>
 hipError_t launch_sk256_t(int variant, const SquareArgs& a, const StreamK& sk, hipStream_t s) {
@@ -732,8 +831,8 @@ hipError_t launch_sk256_t(int variant, const SquareArgs& a, const StreamK& sk, h
         case 1: SP2_L(2, 4, 4, 2, 16, 4, 0); break;
         case 2: SP2_L(2, 2, 4, 4, 32, 2, 0); break;
         case 3: SP2_L(2, 4, 4, 2, 32, 2, 0); break;
-        case 4: SP2_L(2, 2, 4, 4, 32, 2, 4); break;
-        case 5: SP2_L(2, 4, 4, 2, 32, 2, 4); break;
+        case 4: SP2_L(2, 2, 4, 4, 32, 2, 1); break;
+        case 5: SP2_L(2, 4, 4, 2, 32, 2, 1); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -745,8 +844,8 @@ hipError_t launch_sk128_t(int variant, const SquareArgs& a, const StreamK& sk, h
         case 1: SP2_L(2, 2, 2, 2, 64, 2, 0); break;
         case 2: SP2_L(2, 2, 2, 2, 16, 4, 0); break;
         case 3: SP2_L(2, 2, 2, 2, 32, 2, 0); break;
-        case 4: SP2_L(2, 2, 2, 2, 64, 2, 2); break;
-        case 5: SP2_L(2, 2, 2, 2, 32, 2, 4); break;
+        case 4: SP2_L(2, 2, 2, 2, 64, 2, 1); break;
+        case 5: SP2_L(2, 2, 2, 2, 32, 2, 1); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

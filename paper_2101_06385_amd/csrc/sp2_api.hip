@@ -83,9 +83,10 @@ bool sk_wanted(bool split, int tile, int kernel) {
 
 // Persistent variant used when the caller leaves the choice open (index into the
 // per-tile variant table of the kernel), the fastest measured on MI355X: for 256 tiles
-// 8 waves with 32-half slices (one layer at n = 12288: 5.58 ms against 5.63 ms for 4
-// waves; 16384: 11.76 against 12.04 ms); for 128 tiles the 64-half slices.
-int sk_auto_variant(int tile) { return tile == 256 ? 3 : 1; }
+// 8 waves with 32-half slices and the rolling fragment pipeline (one layer, split
+// included, at n = 8192: 1.69 ms against 1.74 ms with two fragment sets; n = 16384: 10.49
+// against 11.02 ms); for 128 tiles the 64-half slices.
+int sk_auto_variant(int tile) { return tile == 256 ? 5 : 1; }
 
 // Resolves the squaring schedule for this device; false = one workgroup per tile.
 bool sk_resolve(const Plan& p, StreamK* sk, int* variant) {
@@ -203,7 +204,7 @@ void make_plan(int n, const Opts& o, Plan* p) {
     p->off_sk_partial = off;
     if (p->sk_capable) off = align_up(off + square_sk_partial_bytes(p->tile_main, p->np));
     p->off_sk_counter = off;
-    if (p->sk_capable) off = align_up(off + sizeof(int) * kMaxSkGrid);
+    if (p->sk_capable) off = align_up(off + sizeof(int) * kSkCounterInts);
     // persistent FP64 layers (refinement on 128 tiles, FP64 mode on 128 tiles)
     p->f64_sk = ((o.refine && p->tile_ref == 128) || (o.precision == SP2_FP64 && p->tile_main == 128)) &&
                 f64_sk_space(p->np);
@@ -513,7 +514,7 @@ int sp2::density_call(const double* dH, int ldh, double* dD, int ldd, int n, int
         if (use_sk) {
             sk.partial = (float*)(ws + p.off_sk_partial);
             sk.counter = (int*)(ws + p.off_sk_counter);
-            SP2_TRY(launch_zero_ints(sk.counter, kMaxSkGrid, s));
+            SP2_TRY(launch_zero_ints(sk.counter, kSkCounterInts, s));
         }
         StreamK f64sk;
         memset(&f64sk, 0, sizeof(f64sk));
@@ -731,7 +732,7 @@ int sp2_fermi_apply(const double* dH, int ldh, double* dD, int ldd, int n, int l
     if (use_sk) {
         sk.partial = (float*)(ws + p.off_sk_partial);
         sk.counter = (int*)(ws + p.off_sk_counter);
-        SP2_TRY(launch_zero_ints(sk.counter, kMaxSkGrid, s));
+        SP2_TRY(launch_zero_ints(sk.counter, kSkCounterInts, s));
     }
     StreamK f64sk;
     memset(&f64sk, 0, sizeof(f64sk));
@@ -857,7 +858,7 @@ size_t sp2_square_workspace_size(int n, int precision, int tile, int kernel) {
     if (split) off = align_up(off + 4 * (size_t)np * plane_ld(np));
     if (sk_wanted(split, t, kernel)) {
         off = align_up(off + square_sk_partial_bytes(t, np));
-        off = align_up(off + sizeof(int) * kMaxSkGrid);
+        off = align_up(off + sizeof(int) * kSkCounterInts);
     }
     if (precision == SP2_FP64 && t == 128 && (kernel == 0 || kernel == 5) && f64_sk_space(np)) {
         off = align_up(off + square_f64_sk_partial_bytes());
@@ -927,7 +928,7 @@ int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int ker
             sk.partial = (float*)(ws + off);
             off = align_up(off + square_sk_partial_bytes(t, np));
             sk.counter = (int*)(ws + off);
-            SP2_TRY(launch_zero_ints(sk.counter, kMaxSkGrid, s));
+            SP2_TRY(launch_zero_ints(sk.counter, kSkCounterInts, s));
             SP2_TRY(launch_square_sk(precision, t, variant, a, sk, s));
         } else {
             SP2_TRY(launch_split_tile_layer(precision, t, kernel, a, s));

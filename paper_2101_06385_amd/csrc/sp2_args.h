@@ -36,6 +36,10 @@ struct SquareArgs {
 // `partial` holds one FP32 tile accumulator per tail chunk, `counter` one arrival count
 // per tail tile (zeroed at the start of every call; each executed layer adds `chunks`).
 constexpr int kMaxSkGrid = 1024;
+// The int array `counter` of the persistent split square: arrivals per split tile at
+// [0, kMaxSkGrid), then the ticket counter of the tail-chunk queue at kSkQueueSlot.
+constexpr int kSkQueueSlot = kMaxSkGrid;
+constexpr int kSkCounterInts = kMaxSkGrid + 64;
 
 // Row stride (elements) of the half-precision planes of an np x np matrix.  With a row
 // pitch of a power of two kilobytes, the rows of one K-slice of a panel fall on the same

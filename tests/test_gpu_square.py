@@ -124,6 +124,7 @@ def test_persistent_schedules_sampled_rows(prec, tile, kernel, n):
 @pytest.mark.parametrize("prec,tile,kernel,n", [
     ("fp16x2", 128, 5, 2048), ("fp16x2", 128, 4, 2048), ("fp16x2", 128, 5, 3000), ("bf16x2", 128, 5, 3000),
     ("fp16x2", 256, 5, 4096), ("fp16x2", 256, 4, 3000), ("fp16x2", 128, 7, 1500),
+    ("fp16x2", 256, 7, 3000), ("bf16x2", 256, 7, 4096), ("fp16x2", 256, 6, 3000), ("fp16x2", 128, 6, 2048),
 ])
 def test_stream_k_schedules_sampled_rows(prec, tile, kernel, n):
     """Fewer tiles than workgroups: the persistent kernel splits the K-slices of all tiles
