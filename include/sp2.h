@@ -174,6 +174,24 @@ int sp2_density(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ
                 const sp2_options* opt, sp2_info* info, void* dWork, size_t work_bytes,
                 void* stream);
 
+/*
+ * sp2_density_static -- sp2_density for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results, with the workspace taken from a scratch array that the library
+ * holds in device memory (SP2_STATIC_SCRATCH_BYTES per device, reserved while the library
+ * is loaded).  The call allocates nothing: no hipMalloc/hipFree, no pinned host memory, no
+ * events.  Problems whose sp2_workspace_size(n, opt) exceeds SP2_STATIC_SCRATCH_BYTES
+ * return SP2_ENOMEM before any work (every n <= 1024 fits, in every precision).
+ * Every call on one device uses that device's single scratch array: calls that overlap
+ * on one device (other streams, other host threads) race and must be serialized by the
+ * caller.  Each call clears the parts of the scratch it relies on, so a call's results do
+ * not depend on earlier calls.  Arguments, stream and info semantics as sp2_density (with
+ * info != NULL the call synchronizes `stream` and copies its state record to *info).
+ */
+#define SP2_STATIC_SCRATCH_BYTES (40u << 20)
+int sp2_density_static(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ, double tol,
+                       const sp2_options* opt, sp2_info* info, void* stream);
+
 /* Phase and per-layer durations of one sp2_density call, from HIP events on `stream`. */
 typedef struct {
     double total_ms;       /* first kernel of the call .. last kernel */

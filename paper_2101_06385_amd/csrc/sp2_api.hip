@@ -641,6 +641,56 @@ int sp2_density(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ
     return density_call(dH, ldh, dD, ldd, n, n_occ, tol, opt, info, dWork, work_bytes, stream, nullptr, true);
 }
 
+}  // extern "C"
+
+// Scratch memory of sp2_density_static: one copy per device (module-scope device array,
+// held while the library is loaded).  Host code never uses the array's name as an address:
+// each device's copy is located once with hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[SP2_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+struct ScratchTable {
+    std::mutex mu;
+    void* addr[kScratchDevices] = {};
+};
+ScratchTable& scratch_table() {
+    static ScratchTable t;
+    return t;
+}
+// Device address of the current device's scratch array (located on the first call on that
+// device, with it current), or nullptr on a HIP error.
+void* device_scratch() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) return nullptr;
+    ScratchTable& t = scratch_table();
+    std::lock_guard<std::mutex> lock(t.mu);
+    if (!t.addr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        t.addr[dev] = ptr;
+    }
+    return t.addr[dev];
+}
+}  // namespace
+
+extern "C" {
+
+int sp2_density_static(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ, double tol,
+                       const sp2_options* opt, sp2_info* info, void* stream) {
+    Opts o;
+    if (!read_opts(opt, &o) || n <= 0 || n > 65536) return SP2_EINVAL;
+    if (ldh < n || ldd < n || n_occ < 0 || n_occ > n || !dH || !dD) return SP2_EINVAL;
+    Plan p;
+    make_plan(n, o, &p);
+    if (p.total > (size_t)SP2_STATIC_SCRATCH_BYTES) return SP2_ENOMEM;
+    void* ws = device_scratch();
+    if (!ws) return SP2_EDEVICE;
+    // no polled host flag (it is pinned memory allocated on first use) and no events
+    return density_call(dH, ldh, dD, ldd, n, n_occ, tol, opt, info, ws, SP2_STATIC_SCRATCH_BYTES, stream, nullptr,
+                        false);
+}
+
 int sp2_density_timed(const double* dH, int ldh, double* dD, int ldd, int n, int n_occ, double tol,
                       const sp2_options* opt, sp2_info* info, void* dWork, size_t work_bytes, void* stream,
                       sp2_timing* timing) {

@@ -108,6 +108,9 @@ def lib() -> ctypes.CDLL:
     L.sp2_density.argtypes = [c_void_p, c_int, c_void_p, c_int, c_int, c_int, c_double, ctypes.POINTER(Options),
                               ctypes.POINTER(Info), c_void_p, c_size_t, c_void_p]
     L.sp2_density.restype = c_int
+    L.sp2_density_static.argtypes = [c_void_p, c_int, c_void_p, c_int, c_int, c_int, c_double,
+                                     ctypes.POINTER(Options), ctypes.POINTER(Info), c_void_p]
+    L.sp2_density_static.restype = c_int
     L.sp2_density_timed.argtypes = L.sp2_density.argtypes + [ctypes.POINTER(Timing)]
     L.sp2_density_timed.restype = c_int
     L.sp2_query.argtypes = [c_void_p, c_int, ctypes.POINTER(Options), ctypes.POINTER(Info), c_void_p]
@@ -320,6 +323,31 @@ def density(h, n_occ: int, tol: float = 0.0, precision="fp16x2", max_layers=100,
         raise SP2Error(st, "sp2_density")
     if timed:
         return out, info_dict(info), timing_dict(tm)
+    return out, (info_dict(info) if info is not None else None)
+
+
+def density_static(h, n_occ: int, tol: float = 0.0, precision="fp16x2", max_layers=100, eps=0.0, bounds=None,
+                   refine=True, scale_log2=-1, want_energy=False, tile=0, kernel=0, out=None, sync=True,
+                   stream=None, gap=None):
+    """sp2_density_static: the density() computation with the library's own per-device scratch
+    memory instead of a workspace (for n up to the scratch size; calls on one device must
+    not overlap).  Returns (D, info) like density()."""
+    import torch
+
+    if not (isinstance(h, torch.Tensor) and h.is_cuda and h.dtype == torch.float64 and h.dim() == 2):
+        raise TypeError("H must be a 2-D float64 CUDA tensor")
+    n = h.shape[0]
+    if h.shape[1] != n or h.stride(1) != 1:
+        raise ValueError("H must be square with unit column stride")
+    opts = options(precision, max_layers, eps, bounds, refine, scale_log2, want_energy, tile, kernel, gap)
+    if out is None:
+        out = torch.empty((n, n), dtype=torch.float64, device=h.device)
+    info = Info() if sync else None
+    st = lib().sp2_density_static(ctypes.c_void_p(h.data_ptr()), h.stride(0), ctypes.c_void_p(out.data_ptr()),
+                                  out.stride(0), n, int(n_occ), float(tol), ctypes.byref(opts),
+                                  ctypes.byref(info) if info is not None else None, _stream_ptr(h.device, stream))
+    if st in (SP2_EDEVICE, SP2_ENOMEM) or (st == SP2_EINVAL and (info is None or int(info.n_padded) == 0)):
+        raise SP2Error(st, "sp2_density_static")
     return out, (info_dict(info) if info is not None else None)
 
 

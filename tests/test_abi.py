@@ -211,3 +211,21 @@ def test_autotune_sizes_and_argument_errors():
     o64 = sp2.options(tile=64)
     assert bw >= sp2.batched_workspace_size([256, 512, 640], o64)
     L.sp2_autotune_reset()
+
+
+def test_static_entry_point_host_checks():
+    """sp2_density_static rejects bad arguments (SP2_EINVAL) and problems whose workspace
+    exceeds its scratch array (SP2_ENOMEM) before touching the device."""
+    L = sp2.lib()
+    o = sp2.options()
+    fake = ctypes.c_void_p(256)   # never dereferenced
+    limit = 40 << 20
+    for prec in ("fp16x2", "bf16x2", "fp32", "fp64"):
+        assert sp2.workspace_size(1024, sp2.options(prec)) <= limit, prec
+    assert sp2.workspace_size(2048, o) > limit
+    assert L.sp2_density_static(fake, 2048, fake, 2048, 2048, 100, 0.0, ctypes.byref(o), None, None) == sp2.SP2_ENOMEM
+    assert L.sp2_density_static(fake, 10, fake, 10, 10, 11, 0.0, ctypes.byref(o), None, None) == sp2.SP2_EINVAL
+    assert L.sp2_density_static(fake, 9, fake, 10, 10, 5, 0.0, ctypes.byref(o), None, None) == sp2.SP2_EINVAL
+    assert L.sp2_density_static(None, 10, fake, 10, 10, 5, 0.0, ctypes.byref(o), None, None) == sp2.SP2_EINVAL
+    bad = sp2.options(max_layers=500)
+    assert L.sp2_density_static(fake, 10, fake, 10, 10, 5, 0.0, ctypes.byref(bad), None, None) == sp2.SP2_EINVAL
