@@ -265,18 +265,16 @@ __global__ __launch_bounds__(256) void k_adjoint_dl(AdjointArgs a, StreamK sk) {
                     for (int q = 0; q < 4; ++q) {
                         f32x4v vv = {acc[0][m][n][4 * q], acc[0][m][n][4 * q + 1], acc[0][m][n][4 * q + 2],
                                      acc[0][m][n][4 * q + 3]};
-                        *wp = vv;
+                        st16_agent(wp, __builtin_bit_cast(u32x4_t, vv));
                         wp += 64;
                     }
-            // release: this partial is in memory before the arrival is counted
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            wait_stores();   // this partial is coherent before the arrival is counted
             __syncthreads();
             if (tid == 0) s_flag = atomicAdd(sk.counter + tail_tile, 1);
             __syncthreads();
             // each layer adds `chunks` arrivals per tail tile: the last one reduces
             finish = ((s_flag + 1) % sk.chunks) == 0;
             if (finish) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // acquire: the other partials are visible
                 const f32x4v* rp = (const f32x4v*)(sk.partial + (size_t)tail_tile * sk.chunks * TILE_F) +
                                    (size_t)wave * NB * NB * 4 * 64 + lane;
                 const size_t cstride = TILE_F / 4;
@@ -286,8 +284,9 @@ __global__ __launch_bounds__(256) void k_adjoint_dl(AdjointArgs a, StreamK sk) {
                     for (int n = 0; n < NB; ++n)
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
-                            f32x4v sum = rp[0];
-                            for (int c = 1; c < sk.chunks; ++c) sum += rp[c * cstride];
+                            f32x4v sum = __builtin_bit_cast(f32x4v, ld16_agent(rp));
+                            for (int c = 1; c < sk.chunks; ++c)
+                                sum += __builtin_bit_cast(f32x4v, ld16_agent(rp + c * cstride));
 #pragma unroll
                             for (int e = 0; e < 4; ++e) acc[0][m][n][4 * q + e] = sum[e];
                             rp += 64;

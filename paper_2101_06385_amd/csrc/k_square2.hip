@@ -60,7 +60,7 @@ bool square_sk_plan(int tile, int variant, int np, int cus, int* wg_per_cu, Stre
     if (tile == 256 || per_cu < 1) per_cu = 1;   // 256 tiles: the accumulators fill the register file
     if (per_cu > 2) per_cu = 2;
     int g = cus * per_cu;
-    if (g > kMaxSkGrid) g = kMaxSkGrid;
+    if (g > kSkGroupSlot) g = kSkGroupSlot;   // chunk partial slots stay below the group slots
     g -= g % 8;
     if (g < 8) return false;
     const int KS = np / V->sk;

@@ -189,26 +189,33 @@ __device__ __forceinline__ void f64_body(const SquareArgs& a, int t, int kb, int
         for (int m = 0; m < kMB; ++m)
 #pragma unroll
             for (int n = 0; n < kNB; ++n) {
-                *wp = acc[m][n];
+                typedef double f64x2 __attribute__((ext_vector_type(2)));
+                const f64x2 lo = {acc[m][n][0], acc[m][n][1]}, hi = {acc[m][n][2], acc[m][n][3]};
+                st16_agent(wp, __builtin_bit_cast(u32x4_t, lo));
+                st16_agent((char*)wp + 16, __builtin_bit_cast(u32x4_t, hi));
                 wp += 64;
             }
-        // release: this partial is in memory before the arrival is counted
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        wait_stores();   // this partial is coherent before the arrival is counted
         __syncthreads();
         if (tid == 0) *s_flag = atomicAdd(sk.counter + tail_tile, 1);
         __syncthreads();
         // each executed layer adds `chunks` arrivals per tail tile: the last one reduces
         if (((*s_flag + 1) % sk.chunks) != 0) return;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // acquire: the other partials are visible
         const f64x4* rp = (const f64x4*)(sk.fpartial + (size_t)tail_tile * sk.chunks * TILE_D) +
                           (size_t)wave * kMB * kNB * 64 + lane;
         const size_t cstride = TILE_D / 4;
+        auto ld = [](const f64x4* q) -> f64x4 {
+            typedef double f64x2 __attribute__((ext_vector_type(2)));
+            const f64x2 lo = __builtin_bit_cast(f64x2, ld16_agent(q));
+            const f64x2 hi = __builtin_bit_cast(f64x2, ld16_agent((const char*)q + 16));
+            return f64x4{lo[0], lo[1], hi[0], hi[1]};
+        };
 #pragma unroll
         for (int m = 0; m < kMB; ++m)
 #pragma unroll
             for (int n = 0; n < kNB; ++n) {
-                f64x4 sum = rp[0];
-                for (int c = 1; c < sk.chunks; ++c) sum += rp[c * cstride];
+                f64x4 sum = ld(rp);
+                for (int c = 1; c < sk.chunks; ++c) sum += ld(rp + c * cstride);
                 acc[m][n] = sum;
                 rp += 64;
             }

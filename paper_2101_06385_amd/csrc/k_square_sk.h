@@ -135,6 +135,10 @@ __device__ __forceinline__ void dma16(const void* g, unsigned lds_base) {
         : "memory", "m0");
 }
 
+// agent-coherent 16-byte store / load of FP32 partials (see st16_agent)
+__device__ __forceinline__ void store_agent(f32x4* p, f32x4 v) { st16_agent(p, __builtin_bit_cast(u32x4_t, v)); }
+__device__ __forceinline__ f32x4 load_agent(const f32x4* p) { return __builtin_bit_cast(f32x4, ld16_agent(p)); }
+
 template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST, int RP>
 struct Cfg {
     static constexpr int NW = WM * WN;
@@ -534,55 +538,38 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
         bool finish = chunk < 0;
         if (!finish) {
             constexpr size_t TILE_F = (size_t)BT * BT;
-            // layout: per wave, per (m, n, quarter), 64 lanes x 4 floats; walked with one
-            // running pointer so that no per-block addresses are kept live
-            f32x4* wp = (f32x4*)(sk.partial + (size_t)slot * TILE_F + (size_t)owave * MB * NB * 16 * 64) + olane;
-            static_for<0, MB>([&](auto m) {
-                static_for<0, NB>([&](auto n) {
-                    static_for<0, 4>([&](auto q4) {
-                        f32x4 vv = {acc[m][n][4 * q4], acc[m][n][4 * q4 + 1], acc[m][n][4 * q4 + 2],
-                                    acc[m][n][4 * q4 + 3]};
-                        *wp = vv;
-                        wp += 64;
+            constexpr size_t cstride = TILE_F / 4;   // f32x4 elements per partial tile
+            // layout: per wave, per (m, n, quarter), 64 lanes x 4 floats
+            f32x4* const wp0 = (f32x4*)(sk.partial + (size_t)owave * MB * NB * 16 * 64) + olane;
+            auto store_partial = [&](size_t pslot) {
+                f32x4* wp = wp0 + pslot * cstride;
+                static_for<0, MB>([&](auto m) {
+                    static_for<0, NB>([&](auto n) {
+                        static_for<0, 4>([&](auto q4) {
+                            f32x4 vv = {acc[m][n][4 * q4], acc[m][n][4 * q4 + 1], acc[m][n][4 * q4 + 2],
+                                        acc[m][n][4 * q4 + 3]};
+                            store_agent(wp, vv);
+                            wp += 64;
+                        });
                     });
                 });
-            });
-            // release: this partial is in memory before the arrival is counted
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __syncthreads();
-            if (tid == 0) s_flag = atomicAdd(sk.counter + tail_tile, 1);
-            __syncthreads();
-            // each executed layer adds `contrib` arrivals per split tile: the last one reduces
-            finish = ((s_flag + 1) % contrib) == 0;
-            if (finish) {
-                // stream-K: the partial slots of the contributors in K order (at most
-                // kSkMaxContrib by the plan); split tail: slots tail_tile * chunks + c
-                if (SQ && tid < contrib) {
-                    const int lo = t * ksq;
-                    const int vf = (int)(((long long)(lo + 1) * G + U - 1) / U) - 1;
-                    const int u = vf + tid;
-                    const int ut0 = (int)((long long)u * U / G) / ksq;
-                    s_slot[tid] = 2 * u + (ut0 == t ? 0 : 1);
-                }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // acquire: the other partials are visible
+                wait_stores();   // this partial is coherent before the arrival is counted
                 __syncthreads();
-                auto slot_of = [&](int c) -> size_t {
-                    return SQ ? (size_t)s_slot[c] : (size_t)tail_tile * sk.chunks + c;
-                };
-                // acc = ((p_0 + p_1) + p_2) + ... in chunk order, one partial at a time: the
-                // loads of a partial are independent and go out in batches of RB row blocks
-                // (as many as the registers freed by the main loop hold)
-                const f32x4* rp0 = (const f32x4*)(sk.partial + (size_t)owave * MB * NB * 16 * 64) + olane;
-                constexpr size_t cstride = TILE_F / 4;   // f32x4 elements per partial tile
+            };
+            // acc = ((p_0 + p_1) + p_2) + ... over the partial slots slot_of(0 .. cnt - 1), one
+            // partial at a time: the loads of a partial are independent and go out in batches
+            // of RB row blocks (as many as the registers freed by the main loop hold)
+            auto sum_partials = [&](int cnt, auto&& slot_of) {
+                const f32x4* rp0 = wp0;
                 constexpr int RB = MB * NB >= 16 ? 1 : (MB >= 2 ? 2 : 1);
-                for (int c = 0; c < contrib; ++c) {
+                for (int c = 0; c < cnt; ++c) {
                     const f32x4* rp = rp0 + slot_of(c) * cstride;
                     static_for<0, MB / RB>([&](auto mb) {
                         f32x4 pv[RB][NB][4];
                         static_for<0, RB>([&](auto r) {
                             static_for<0, NB>([&](auto n) {
                                 static_for<0, 4>([&](auto q4) {
-                                    pv[r][n][q4] = rp[(((mb * RB + r) * NB + n) * 4 + q4) * 64];
+                                    pv[r][n][q4] = load_agent(rp + (((mb * RB + r) * NB + n) * 4 + q4) * 64);
                                 });
                             });
                         });
@@ -599,6 +586,49 @@ __device__ __forceinline__ void sk_body(const SquareArgs& a, const StreamK& sk, 
                         });
                         __builtin_amdgcn_sched_barrier(0);
                     });
+                }
+            };
+            // Split tail with a multiple of 4 chunks per tile: two levels, so that no single
+            // workgroup reads all the partials of a tile.  The last of each group of 4
+            // consecutive chunks sums them (in chunk order) into a group partial; the last
+            // group of the tile sums the group partials (in group order).  Counters: tile
+            // arrivals at [0, tail_tiles), group arrivals from kSkGroupCounter; group partial
+            // slots from kSkGroupSlot.
+            const int gs = (!SQ && sk.chunks > 4 && sk.chunks % 4 == 0) ? 4 : contrib;
+            const int ng = contrib / gs;                      // groups per tile (1: one level)
+            const int grp = ng > 1 ? chunk / gs : 0;
+            store_partial(slot);
+            if (tid == 0) {
+                int* cnt1 = ng > 1 ? sk.counter + kSkGroupCounter + tail_tile * ng + grp : sk.counter + tail_tile;
+                s_flag = atomicAdd(cnt1, 1);
+            }
+            __syncthreads();
+            // each executed layer adds gs arrivals per group (per tile with one level): the
+            // last one reduces
+            finish = ((s_flag + 1) % gs) == 0;
+            if (finish) {
+                // stream-K: the partial slots of the contributors in K order (at most
+                // kSkMaxContrib by the plan); split tail: slots tail_tile * chunks + c
+                if (SQ && tid < contrib) {
+                    const int lo = t * ksq;
+                    const int vf = (int)(((long long)(lo + 1) * G + U - 1) / U) - 1;
+                    const int u = vf + tid;
+                    const int ut0 = (int)((long long)u * U / G) / ksq;
+                    s_slot[tid] = 2 * u + (ut0 == t ? 0 : 1);
+                }
+                __syncthreads();
+                const size_t first = (size_t)tail_tile * sk.chunks + (size_t)grp * gs;
+                sum_partials(gs, [&](int c) -> size_t { return SQ ? (size_t)s_slot[c] : first + c; });
+                if (ng > 1) {
+                    const size_t gslot0 = (size_t)kSkGroupSlot + (size_t)tail_tile * ng;
+                    __syncthreads();   // every wave has read the chunk partials
+                    store_partial(gslot0 + grp);
+                    if (tid == 0) s_flag = atomicAdd(sk.counter + tail_tile, 1);
+                    __syncthreads();
+                    finish = ((s_flag + 1) % ng) == 0;
+                    if (finish) {
+                        sum_partials(ng, [&](int g) -> size_t { return gslot0 + g; });
+                    }
                 }
             }
         }

@@ -40,6 +40,11 @@ constexpr int kMaxSkGrid = 1024;
 // [0, kMaxSkGrid), then the ticket counter of the tail-chunk queue at kSkQueueSlot.
 constexpr int kSkQueueSlot = kMaxSkGrid;
 constexpr int kSkCounterInts = kMaxSkGrid + 64;
+// Two-level split tail: group arrival counters at [kSkGroupCounter, kMaxSkGrid) of
+// `counter`, group partial tiles from slot kSkGroupSlot of `partial` (chunk partials use
+// slots below it: at most one per workgroup).
+constexpr int kSkGroupCounter = kMaxSkGrid / 2;
+constexpr int kSkGroupSlot = kMaxSkGrid / 2;
 
 // Row stride (elements) of the half-precision planes of an np x np matrix.  With a row
 // pitch of a power of two kilobytes, the rows of one K-slice of a panel fall on the same

@@ -10,6 +10,25 @@
 
 namespace sp2 {
 
+// Split-K partial tiles of the persistent kernels cross XCDs, whose L2 caches are not
+// coherent with each other.  They are written with agent-coherent (write-through) stores
+// and read with agent-scope atomic loads, so neither side needs a device-wide fence: such a
+// fence writes back or invalidates the whole L2 of the XCD, which also holds the other
+// workgroups' panels and output.  A writer waits for its stores (wait_stores) before its
+// arrival is counted.
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st16_agent(void* p, u32x4_t v) {
+    asm volatile("global_store_dwordx4 %0, %1, off sc1" : : "v"(p), "v"(v) : "memory");
+}
+__device__ __forceinline__ u32x4_t ld16_agent(const void* p) {
+    typedef unsigned long long u64x2_t __attribute__((ext_vector_type(2)));
+    const unsigned long long* q = (const unsigned long long*)p;
+    const u64x2_t ab = {__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                        __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
+    return __builtin_bit_cast(u32x4_t, ab);
+}
+__device__ __forceinline__ void wait_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 // ---------------------------------------------------------------------------------
 // Per-call device state: lives at the start of the caller's workspace.
 // Written by the control kernels; read by the layer kernels (skip flag, layer

@@ -92,11 +92,14 @@ def test_plain_square_vs_fp64(prec, tile, n):
     ("fp16x2", 256, 6, 6100), ("fp16x2", 256, 7, 6100), ("fp16x2", 128, 6, 4100), ("fp16x2", 128, 7, 4100),
     ("bf16x2", 256, 3, 6100), ("bf16x2", 128, 3, 4100), ("bf16x2", 256, 7, 6100), ("fp16x2", 256, 1, 6100),
     ("fp16x2", 128, 1, 4100), ("bf16x2", 128, 1, 4100), ("fp16x2", 256, 8, 6100), ("fp16x2", 128, 8, 4100),
+    ("fp16x2", 256, 7, 8000), ("bf16x2", 256, 5, 8000),
 ])
 def test_persistent_schedules_sampled_rows(prec, tile, kernel, n):
     """Persistent schedules, every kernel variant (only used once there are at least as
-    many tiles as workgroups, hence the large n; 300 and 561 tiles leave a split tail):
-    sampled rows against the oracle's exact products."""
+    many tiles as workgroups, hence the large n; 300 and 561 tiles leave a split tail in
+    5 and 2 chunks per tile, summed in one level; n = 8000 pads to 528 tiles of 256, whose
+    16 leftover tiles are cut into 16 chunks and summed in two levels of 4): sampled rows
+    against the oracle's exact products."""
     fmt = "fp16" if prec == "fp16x2" else "bf16"
     s = 12 if fmt == "fp16" else 0
     rng = np.random.default_rng(n + kernel)
