@@ -239,7 +239,7 @@ int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int ker
                size_t work_bytes, void* stream);
 
 /*
- * sp2_density_batched -- sp2_density for `batch` independent Hamiltonians of (possibly)
+ * sp2_density_batched -- sp2_density for `batch` (1..8192) independent Hamiltonians of (possibly)
  * different sizes in one go: the batching of many small matrix products that the paper
  * (Sec. "Mixed Precision Fermi-operator expansion on tensor cores", its closing remark on
  * small N) expects to carry the SP2 recursion's rate to small matrices.  All arrays are HOST arrays of length `batch`; dH[i], dD[i]

@@ -3,5 +3,5 @@
 
 namespace sp2 {
 template hipError_t launch_dp_t<__bf16>(int tile, int variant, const SquareArgs& a, const SquareArgs* descs,
-                                     const int* offs, int nprob, int blocks, hipStream_t s);
+                                     const int* map, int per, hipStream_t s);
 }  // namespace sp2

@@ -19,11 +19,11 @@ hipError_t launch_sk_t(int tile, int variant, const SquareArgs& a, const StreamK
     return hipErrorInvalidValue;
 }
 template <typename T16>
-hipError_t launch_dp_t(int tile, int variant, const SquareArgs& a, const SquareArgs* descs, const int* offs,
-                       int nprob, int blocks, hipStream_t s);
+hipError_t launch_dp_t(int tile, int variant, const SquareArgs& a, const SquareArgs* descs, const int* map, int per,
+                       hipStream_t s);
 extern template hipError_t launch_dp_t<_Float16>(int, int, const SquareArgs&, const SquareArgs*, const int*, int,
-                                                 int, hipStream_t);
-extern template hipError_t launch_dp_t<__bf16>(int, int, const SquareArgs&, const SquareArgs*, const int*, int, int,
+                                                 hipStream_t);
+extern template hipError_t launch_dp_t<__bf16>(int, int, const SquareArgs&, const SquareArgs*, const int*, int,
                                                hipStream_t);
 
 // Variants of the persistent kernel per tile edge: (waves, slice width in halves, LDS
@@ -103,15 +103,15 @@ hipError_t launch_square_sk(int precision, int tile, int variant, const SquareAr
 
 namespace sp2 {
 hipError_t launch_square_dp(int precision, int tile, int variant, const SquareArgs& a, hipStream_t s) {
-    if (precision == SP2_FP16X2) return launch_dp_t<_Float16>(tile, variant, a, nullptr, nullptr, 0, 0, s);
-    if (precision == SP2_BF16X2) return launch_dp_t<__bf16>(tile, variant, a, nullptr, nullptr, 0, 0, s);
+    if (precision == SP2_FP16X2) return launch_dp_t<_Float16>(tile, variant, a, nullptr, nullptr, 0, s);
+    if (precision == SP2_BF16X2) return launch_dp_t<__bf16>(tile, variant, a, nullptr, nullptr, 0, s);
     return hipErrorInvalidValue;
 }
-hipError_t launch_square_dp_g(int precision, int tile, int variant, const SquareArgs* descs, const int* offs,
-                              int nprob, int blocks, hipStream_t s) {
+hipError_t launch_square_dp_g(int precision, int tile, int variant, const SquareArgs* descs, const int* map, int per,
+                              hipStream_t s) {
     const SquareArgs unused{};
-    if (precision == SP2_FP16X2) return launch_dp_t<_Float16>(tile, variant, unused, descs, offs, nprob, blocks, s);
-    if (precision == SP2_BF16X2) return launch_dp_t<__bf16>(tile, variant, unused, descs, offs, nprob, blocks, s);
+    if (precision == SP2_FP16X2) return launch_dp_t<_Float16>(tile, variant, unused, descs, map, per, s);
+    if (precision == SP2_BF16X2) return launch_dp_t<__bf16>(tile, variant, unused, descs, map, per, s);
     return hipErrorInvalidValue;
 }
 }  // namespace sp2

@@ -319,14 +319,15 @@ __global__ __launch_bounds__(128 * WN) void k_square_f64_sk(SquareArgs a, Stream
     }
 }
 
-// grouped: block b of problem p (offs[p] <= b < offs[p + 1]) computes tile b - offs[p]
+// grouped: block b computes the tile that the tile map names for it (see kTileMapShift)
 template <int ST, int WN>
 __global__ __launch_bounds__(128 * WN) void k_square_f64_g(const SquareArgs* __restrict__ descs,
-                                                          const int* __restrict__ offs, int nprob) {
+                                                          const int* __restrict__ map, int per) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[ST * kStage];
     __shared__ double red[4 * WN];
-    const int p = find_group(offs, nprob, blockIdx.x);
-    const SquareArgs a = descs[p];
+    const int e = map[(blockIdx.x & 7) * per + (blockIdx.x >> 3)];
+    if (e < 0) return;
+    const SquareArgs a = descs[e >> kTileMapShift];
     if (a.skip && *a.skip) return;
     __shared__ int s_flag;
     StreamK none;
@@ -337,14 +338,14 @@ __global__ __launch_bounds__(128 * WN) void k_square_f64_g(const SquareArgs* __r
     none.partial = nullptr;
     none.counter = nullptr;
     none.fpartial = nullptr;
-    f64_body<ST, WN>(a, blockIdx.x - offs[p], 0, a.np / kBK, -1, 0, 0, none, lds, red, &s_flag);
+    f64_body<ST, WN>(a, e & kTileMapMask, 0, a.np / kBK, -1, 0, 0, none, lds, red, &s_flag);
 }
 
 }  // namespace
 
-// grouped FP64 layer on 128 tiles (8 waves, 4 stages) over nprob problems
-hipError_t launch_square_f64_g(const SquareArgs* descs, const int* offs, int nprob, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_square_f64_g<4, 4>), dim3(blocks), dim3(512), 0, s, descs, offs, nprob);
+// grouped FP64 layer on 128 tiles (8 waves, 4 stages) over a tile map
+hipError_t launch_square_f64_g(const SquareArgs* descs, const int* map, int per, hipStream_t s) {
+    hipLaunchKernelGGL((k_square_f64_g<4, 4>), dim3(8 * per), dim3(512), 0, s, descs, map, per);
     return hipGetLastError();
 }
 

@@ -775,7 +775,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_sk(SquareArgs a, Stream
 }
 
 // One workgroup per upper-triangle tile of one problem, XCD-aware tile order.
-template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST>
+template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST, int RP>
 __global__ __launch_bounds__(64 * WM * WN) void k_square_dp(SquareArgs a) {
     if (a.skip && *a.skip) return;
     const int t = xcd_tile_index(blockIdx.x, a.per, a.ntiles);
@@ -788,17 +788,17 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_dp(SquareArgs a) {
     none.partial = nullptr;
     none.counter = nullptr;
     none.fpartial = nullptr;
-    sk_body<T16, WM, WN, MB, NB, SK, ST, 0, true>(a, none, 0, t);
+    sk_body<T16, WM, WN, MB, NB, SK, ST, RP, true>(a, none, 0, t);
 }
 
-// One workgroup per upper-triangle tile, for one problem (descs[0], offs = {0, ntiles})
-// or many: block b belongs to problem p with offs[p] <= b < offs[p + 1] and computes its
-// tile b - offs[p].
-template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST>
+// One workgroup per upper-triangle tile of many problems: block b computes the tile that
+// the tile map names for it (see kTileMapShift), if any.
+template <typename T16, int WM, int WN, int MB, int NB, int SK, int ST, int RP>
 __global__ __launch_bounds__(64 * WM * WN) void k_square_dp_g(const SquareArgs* __restrict__ descs,
-                                                             const int* __restrict__ offs, int nprob) {
-    const int p = find_group(offs, nprob, blockIdx.x);
-    const SquareArgs a = descs[p];
+                                                             const int* __restrict__ map, int per) {
+    const int e = map[(blockIdx.x & 7) * per + (blockIdx.x >> 3)];
+    if (e < 0) return;
+    const SquareArgs a = descs[e >> kTileMapShift];
     if (a.skip && *a.skip) return;
     StreamK none;
     none.grid = 0;
@@ -808,38 +808,39 @@ __global__ __launch_bounds__(64 * WM * WN) void k_square_dp_g(const SquareArgs* 
     none.partial = nullptr;
     none.counter = nullptr;
     none.fpartial = nullptr;
-    sk_body<T16, WM, WN, MB, NB, SK, ST, 0, true>(a, none, 0, blockIdx.x - offs[p]);
+    sk_body<T16, WM, WN, MB, NB, SK, ST, RP, true>(a, none, 0, e & kTileMapMask);
 }
 
 }  // namespace
 
 // Per-tile (one workgroup per tile) forms of the same pipeline.  Variants per tile edge,
-// as (waves, K-slice halves, LDS stages): 256: (8, 32, 2), (4, 32, 2); 128: (4, 32, 2),
-// (4, 64, 2), (4, 16, 4).  descs == nullptr: the single problem `a` (XCD-aware order, grid
-// 8 a.per); otherwise the grouped launch over nprob problems (blocks = offs[nprob]).
+// as (waves, K-slice halves, LDS stages, rolling fragment pipeline): 256: (8, 32, 2, 1),
+// (4, 32, 2, 0); 128: (4, 32, 2, 1), (4, 64, 2, 0), (4, 16, 4, 0).  descs == nullptr: the
+// single problem `a` (XCD-aware order, grid 8 a.per); otherwise the grouped launch over
+// the tile map (grid 8 per).
 template <typename T16>
-hipError_t launch_dp_t(int tile, int variant, const SquareArgs& a, const SquareArgs* descs, const int* offs,
-                       int nprob, int blocks, hipStream_t s) {
-#define SP2_L(WM, WN, MB, NB, SK, ST)                                                                       \
+hipError_t launch_dp_t(int tile, int variant, const SquareArgs& a, const SquareArgs* descs, const int* map,
+                       int per, hipStream_t s) {
+#define SP2_L(WM, WN, MB, NB, SK, ST, RP)                                                                   \
     do {                                                                                                   \
         if (descs)                                                                                         \
-            hipLaunchKernelGGL((k_square_dp_g<T16, WM, WN, MB, NB, SK, ST>), dim3(blocks), dim3(64 * WM * WN), \
-                               0, s, descs, offs, nprob);                                                  \
+            hipLaunchKernelGGL((k_square_dp_g<T16, WM, WN, MB, NB, SK, ST, RP>), dim3(8 * per),           \
+                               dim3(64 * WM * WN), 0, s, descs, map, per);                                 \
         else                                                                                               \
-            hipLaunchKernelGGL((k_square_dp<T16, WM, WN, MB, NB, SK, ST>), dim3(8 * a.per), dim3(64 * WM * WN), \
-                               0, s, a);                                                                   \
+            hipLaunchKernelGGL((k_square_dp<T16, WM, WN, MB, NB, SK, ST, RP>), dim3(8 * a.per),           \
+                               dim3(64 * WM * WN), 0, s, a);                                               \
     } while (0)
     if (tile == 256) {
         switch (variant) {
-            case 0: SP2_L(2, 4, 4, 2, 32, 2); break;
-            case 1: SP2_L(2, 2, 4, 4, 32, 2); break;
+            case 0: SP2_L(2, 4, 4, 2, 32, 2, 1); break;
+            case 1: SP2_L(2, 2, 4, 4, 32, 2, 0); break;
             default: return hipErrorInvalidValue;
         }
     } else if (tile == 128) {
         switch (variant) {
-            case 0: SP2_L(2, 2, 2, 2, 32, 2); break;
-            case 1: SP2_L(2, 2, 2, 2, 64, 2); break;
-            case 2: SP2_L(2, 2, 2, 2, 16, 4); break;
+            case 0: SP2_L(2, 2, 2, 2, 32, 2, 1); break;
+            case 1: SP2_L(2, 2, 2, 2, 64, 2, 0); break;
+            case 2: SP2_L(2, 2, 2, 2, 16, 4, 0); break;
             default: return hipErrorInvalidValue;
         }
     } else {

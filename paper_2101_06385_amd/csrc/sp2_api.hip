@@ -8,6 +8,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -1019,9 +1020,41 @@ struct BatchLayout {
     std::vector<int> nontrivial;        // indices of problems that run the recursion
     std::vector<Plan> plans;
     std::vector<size_t> region;         // byte offset of each problem's region
-    size_t off_probs, off_sq, off_offs, total;
+    size_t off_probs, off_sq, off_offs, off_map, total;
     int n_offs;                         // stride of the offset arrays (batch + 1)
+    size_t map_ints;                    // capacity of the tile map of the 128-tile grouped launches
 };
+
+// Tile map of the grouped 128-tile launches (squaring and FP64 refinement): every tile of
+// the problems `order` lists, each problem's tiles on one XCD (so they share its L2),
+// problems taken largest first and given to the XCD with the least work so far (work ~ n_p^3).
+// Returns per (map entries per XCD); map has 8 per entries.
+int build_tile_map(const std::vector<Plan>& plans, const std::vector<int>& problems, std::vector<int>* map) {
+    std::vector<int> order(problems.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return plans[problems[x]].np > plans[problems[y]].np;
+    });
+    std::vector<int> bins[8];
+    double load[8] = {};
+    for (int k : order) {
+        const Plan& p = plans[problems[k]];
+        int x = 0;
+        for (int j = 1; j < 8; ++j)
+            if (load[j] < load[x]) x = j;
+        for (int t = 0; t < p.main_tiles; ++t) bins[x].push_back((k << kTileMapShift) | t);
+        load[x] += (double)p.np * p.np * p.np;
+    }
+    size_t per = 0;
+    for (auto& b : bins) per = b.size() > per ? b.size() : per;
+    map->assign(8 * per, -1);
+    for (int x = 0; x < 8; ++x)
+        for (size_t j = 0; j < bins[x].size(); ++j) (*map)[x * per + j] = bins[x][j];
+    return (int)per;
+}
+
+// problems of one batched call: the tile map encodes the problem in the bits above kTileMapShift
+constexpr int kMaxBatch = 1 << (31 - kTileMapShift);
 
 bool batch_layout(int batch, const int* n, const int* n_occ, const Opts& o, BatchLayout* L) {
     L->batch = batch;
@@ -1053,6 +1086,11 @@ bool batch_layout(int batch, const int* n, const int* n_occ, const Opts& o, Batc
     off = align_up(off + sizeof(SquareArgs) * 4 * batch);   // even layer, odd layer, refine 1, refine 2
     L->off_offs = off;
     off = align_up(off + sizeof(int) * 5 * L->n_offs);      // gersh, init, main, ref, dstats
+    L->map_ints = 0;
+    if (L->tile == 128)
+        for (int i = 0; i < batch; ++i) L->map_ints += 8 * (size_t)L->plans[i].main_tiles;
+    L->off_map = off;
+    off = align_up(off + sizeof(int) * L->map_ints);
     // then one single-problem region per problem; its DevState sits at the region's start
     for (int i = 0; i < batch; ++i) {
         L->region[i] = off;
@@ -1074,7 +1112,7 @@ bool batch_opts(const sp2_options* opt, Opts* o) {
 }  // namespace
 
 size_t sp2_batched_workspace_size(int batch, const int* n, const sp2_options* opt) {
-    if (batch <= 0 || !n) return 0;
+    if (batch <= 0 || batch > kMaxBatch || !n) return 0;
     Opts o;
     if (!batch_opts(opt, &o)) return 0;
     for (int i = 0; i < batch; ++i)
@@ -1092,7 +1130,9 @@ static int run_batched(int batch, const double* const* dH, const int* ldh, doubl
                        const sp2_options* opt, sp2_info* infos, int use_graph, void* dWork, size_t work_bytes,
                        void* stream) {
     Opts o;
-    if (batch <= 0 || !dH || !ldh || !dD || !ldd || !n || !n_occ || !dWork || !batch_opts(opt, &o)) return SP2_EINVAL;
+    if (batch <= 0 || batch > kMaxBatch || !dH || !ldh || !dD || !ldd || !n || !n_occ || !dWork ||
+        !batch_opts(opt, &o))
+        return SP2_EINVAL;
     if (((uintptr_t)dWork) % kAlign) return SP2_EINVAL;
     if ((homo == nullptr) != (lumo == nullptr)) return SP2_EINVAL;
     for (int i = 0; i < batch; ++i) {
@@ -1211,6 +1251,14 @@ static int run_batched(int batch, const double* const* dH, const int* ldh, doubl
         SP2_TRY(hipStreamSynchronize(user));
         SP2_TRY(hipMemcpy(d_probs, probs.data(), sizeof(BatchProblem) * nt, hipMemcpyHostToDevice));
         SP2_TRY(hipMemcpy(ws + L.off_sq, sq.data(), sizeof(SquareArgs) * 4 * nt, hipMemcpyHostToDevice));
+        int map_per = 0;
+        if (L.tile == 128) {
+            std::vector<int> map;
+            map_per = build_tile_map(L.plans, L.nontrivial, &map);
+            if (map.size() > L.map_ints) return SP2_EINVAL;
+            SP2_TRY(hipMemcpy(ws + L.off_map, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice));
+        }
+        const int* d_map = (const int*)(ws + L.off_map);
         SP2_TRY(hipMemcpy(ws + L.off_offs, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice));
         for (int k = 0; k < nt; ++k)
             SP2_TRY(hipMemcpy(ws + L.region[L.nontrivial[k]], &states[k], sizeof(DevState), hipMemcpyHostToDevice));
@@ -1236,12 +1284,12 @@ static int run_batched(int batch, const double* const* dH, const int* ldh, doubl
                 if (o.precision == SP2_FP32)
                     SP2_TRY(launch_square_plain_g(SP2_FP32, L.tile, a, d_om, nt, o_m[nt], s));
                 else
-                    SP2_TRY(L.tile == 128 ? launch_square_dp_g(o.precision, 128, 0, a, d_om, nt, o_m[nt], s)
+                    SP2_TRY(L.tile == 128 ? launch_square_dp_g(o.precision, 128, 0, a, d_map, map_per, s)
                                           : launch_square_split_g(o.precision, L.tile, a, d_om, nt, o_m[nt], s));
             }
             SP2_TRY(launch_batch_select(d_probs, nt, 64, s));
             for (int step = 2; step <= 3; ++step)
-                SP2_TRY(L.tile == 128 ? launch_square_f64_g(d_sq + step * nt, d_or, nt, o_r[nt], s)
+                SP2_TRY(L.tile == 128 ? launch_square_f64_g(d_sq + step * nt, d_map, map_per, s)
                                       : launch_square_plain_g(SP2_FP64, L.tile, d_sq + step * nt, d_or, nt, o_r[nt], s));
             SP2_TRY(launch_batch_dstats(d_probs, d_od, nt, o_d[nt], s));
             SP2_TRY(launch_batch_finalize(d_probs, nt, s));

@@ -46,6 +46,12 @@ constexpr int kSkCounterInts = kMaxSkGrid + 64;
 constexpr int kSkGroupCounter = kMaxSkGrid / 2;
 constexpr int kSkGroupSlot = kMaxSkGrid / 2;
 
+// Tile maps of the grouped (many-problem) launches: entry (problem << kTileMapShift) |
+// tile, or -1 for no work.  Block b reads entry (b mod 8) * per + b / 8, so the blocks that
+// the hardware sends to one XCD (b mod 8 fixed) walk that XCD's part of the map.
+constexpr int kTileMapShift = 18;
+constexpr int kTileMapMask = (1 << kTileMapShift) - 1;
+
 // Row stride (elements) of the half-precision planes of an np x np matrix.  With a row
 // pitch of a power of two kilobytes, the rows of one K-slice of a panel fall on the same
 // L2 channel; one extra 128-byte line per row spreads them.  One squaring layer at

@@ -186,7 +186,8 @@ hipError_t launch_square_split(int precision, int tile, const SquareArgs& a, hip
 hipError_t launch_square_plain(int precision, int tile, const SquareArgs& a, hipStream_t s);
 // FP64 layer with direct-to-LDS staging, 128 tiles (k_square_f64.hip); variant 0 or 1
 hipError_t launch_square_f64(int variant, const SquareArgs& a, hipStream_t s);
-hipError_t launch_square_f64_g(const SquareArgs* descs, const int* offs, int nprob, int blocks, hipStream_t s);
+// grouped FP64 layer over a tile map (see kTileMapShift), grid 8 per
+hipError_t launch_square_f64_g(const SquareArgs* descs, const int* map, int per, hipStream_t s);
 // persistent FP64 layer (whole rounds + split-K tail), 128 tiles
 bool square_f64_sk_plan(int np, int cus, StreamK* sk);
 size_t square_f64_sk_partial_bytes();
@@ -204,8 +205,8 @@ hipError_t launch_square_sk(int precision, int tile, int variant, const SquareAr
                             hipStream_t s);
 // the same pipeline with one workgroup per tile (tiles 128, 256): one problem, or grouped
 hipError_t launch_square_dp(int precision, int tile, int variant, const SquareArgs& a, hipStream_t s);
-hipError_t launch_square_dp_g(int precision, int tile, int variant, const SquareArgs* descs, const int* offs,
-                              int nprob, int blocks, hipStream_t s);
+hipError_t launch_square_dp_g(int precision, int tile, int variant, const SquareArgs* descs, const int* map, int per,
+                              hipStream_t s);
 hipError_t launch_zero_ints(int* p, int count, hipStream_t s);
 
 // preparation / control kernels (k_prep.hip)
