@@ -110,3 +110,68 @@ def finite_difference_grad(lam0, target_vals, w, b, c, h=1e-4):
             g[k] = (loss_scalar(lam0, target_vals, *pp) - loss_scalar(lam0, target_vals, *pm)) / (2 * h)
         out.append(g)
     return out
+
+
+def loss_grad_scalar_perturbed(lam0, target_vals, w, b, c, layer=None, delta=0.0):
+    """loss_grad_scalar with delta added to every eigenvalue image right after layer `layer`
+    (x_{layer+1} += delta), the rest of the chain recomputed from there: the effect of one
+    layer's output error on the loss and gradient."""
+    xs = [np.asarray(lam0, dtype=np.float64)]
+    for k in range(len(w)):
+        x = xs[-1]
+        y = w[k] * x * x + b[k] * x + c[k]
+        if layer == k:
+            y = y + delta
+        xs.append(y)
+    diff = xs[-1] - target_vals
+    g = 2.0 * diff
+    kk = len(w)
+    dw, db, dc = np.zeros(kk), np.zeros(kk), np.zeros(kk)
+    for k in range(kk - 1, -1, -1):
+        x = xs[k]
+        dw[k] = float(np.sum(g * x * x))
+        db[k] = float(np.sum(g * x))
+        dc[k] = float(np.sum(g))
+        g = g * (2.0 * w[k] * x + b[k])
+    return float(np.sum(diff * diff)), dw, db, dc, xs
+
+
+def gradient_error_bound(lam0, target_vals, w, b, c, rel_err):
+    """First-order bound of the error in (dL/dW, dL/dB, dL/dc) that layer outputs carrying
+    errors of at most rel_err * max|x_{k+1}| (per eigenvalue) cause: for each layer the
+    gradient is recomputed with every eigenvalue image shifted by +-that amount (the
+    coherent, worst-sign case of the sums over eigenvalues), and the larger change is
+    summed over the layers.  Returns three arrays (W, B, c)."""
+    _, w0, b0, c0, xs = loss_grad_scalar_perturbed(lam0, target_vals, w, b, c)
+    g0 = np.concatenate([w0, b0, c0])
+    tot = np.zeros_like(g0)
+    for k in range(len(w)):
+        e = rel_err * float(np.abs(xs[k + 1]).max())
+        worst = np.zeros_like(g0)
+        for s in (1.0, -1.0):
+            _, wp, bp, cp, _ = loss_grad_scalar_perturbed(lam0, target_vals, w, b, c, k, s * e)
+            worst = np.maximum(worst, np.abs(np.concatenate([wp, bp, cp]) - g0))
+        tot += worst
+    kk = len(w)
+    return tot[:kk], tot[kk:2 * kk], tot[2 * kk:]
+
+
+def adam_scalar(lam0, target_vals, w, b, c, lr, steps, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Adam (Kingma and Ba, with bias-corrected moments) on the eigenvalue-space loss of the
+    network, in FP64: the fit of the per-layer coefficients, written out step by step.
+    Returns (loss before each step, final W, B, c)."""
+    kk = len(w)
+    p = np.concatenate([np.asarray(w, np.float64), np.asarray(b, np.float64), np.asarray(c, np.float64)])
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    losses = []
+    for t in range(1, steps + 1):
+        loss, dw, db, dc, _ = loss_grad_scalar(lam0, target_vals, p[:kk], p[kk:2 * kk], p[2 * kk:])
+        losses.append(loss)
+        g = np.concatenate([dw, db, dc])
+        m = beta1 * m + (1.0 - beta1) * g
+        v = beta2 * v + (1.0 - beta2) * g * g
+        mhat = m / (1.0 - beta1 ** t)
+        vhat = v / (1.0 - beta2 ** t)
+        p = p - lr * mhat / (np.sqrt(vhat) + eps)
+    return np.array(losses), p[:kk], p[kk:2 * kk], p[2 * kk:]

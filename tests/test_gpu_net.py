@@ -191,9 +191,52 @@ def test_config5_full_size_loss_and_gradient():
     loss = float((diff ** 2).sum())
     dw, db, dc, _ = sp2.net_backward((2.0 * diff).float(), _t(wt), _t(bt), _t(ct), ws, precision="fp16x2",
                                      want_g0=False)
-    rl, rw, rb, rc, _ = onet.loss_grad_scalar(lam0, tvals, wt.astype(np.float64), bt.astype(np.float64),
-                                              ct.astype(np.float64))
+    w64, b64, c64 = wt.astype(np.float64), bt.astype(np.float64), ct.astype(np.float64)
+    rl, rw, rb, rc, _ = onet.loss_grad_scalar(lam0, tvals, w64, b64, c64)
     assert abs(loss - rl) <= 1e-3 * rl + 1e-2, (loss, rl)
-    for got, ref in ((dw, rw), (db, rb), (dc, rc)):
+    # Tolerance from the layer error bound: each FP16X2 layer output carries at most
+    # 2 u16^2 (the split representation, u16 = 2^-11) plus sqrt(n) u32 (FP32 accumulation
+    # over n terms, u32 = 2^-24) of max|x|; the FP32 adjoint layers another sqrt(n) u32.
+    # gradient_error_bound propagates that through the rest of the chain (worst sign).
+    rel = 2 * 2.0 ** -22 + 2 * np.sqrt(n) * 2.0 ** -24
+    tw, tb, tc = onet.gradient_error_bound(lam0, tvals, w64, b64, c64, rel)
+    for got, ref, tol in ((dw, rw, tw), (db, rb, tb), (dc, rc, tc)):
         g = got.cpu().numpy().astype(np.float64)
-        assert np.abs(g - ref).max() <= 2e-2 * np.abs(ref).max() + 1e-3, (g[:4], ref[:4])
+        print("C5 gradient: max |err| / derived bound = %.3f" % float((np.abs(g - ref) / tol).max()))
+        assert np.all(np.abs(g - ref) <= tol), (g[:4], ref[:4], tol[:4])
+
+
+def test_config5_fit_tracks_the_oracle():
+    """The C5 fit: the N = 2048, 20-layer FP16X2 network trained with Adam (lr 3e-3, 150
+    steps) on the kT = 0.2 eV target from the truncated-SP2 start, against the oracle's
+    FP64 Adam on the exact eigenvalue loss from the same start.  The GPU loss stays within
+    1 % of the oracle's at every step (measured: 1e-4), and the fit ends below 0.45 of the
+    starting loss (both reach 0.41: 54.7 -> 22.2)."""
+    n, k, lr, steps = 2048, 20, 3e-3, 150
+    w = wl.config5(seed=5000, n=n)
+    e1, en = osp2.gershgorin(w.h)
+    x0 = osp2.rescale(w.h, e1, en).astype(np.float32)
+    lam0 = (en - w.eps) / (en - e1)
+    tvals = dm.fermi_dirac(w.eps, 0.0, 0.2)
+    sig = (list(osp2.sp2_eigen(lam0, n // 2, max_layers=k).sigma) + [1, -1] * k)[:k]
+    wt, bt, ct = onet.sp2_branch_coefficients(sig)
+    ref, *_ = onet.adam_scalar(lam0, tvals, wt, bt, ct, lr, steps)
+    model = gnet.SP2Net(sig, precision="fp16x2", device=DEV)
+    xt = _t(x0)
+    tt = _t(dm.dm_fermi(w.q, w.eps, 0.0, 0.2))
+    opt = torch.optim.Adam(model.parameters(), lr=lr)
+    got = []
+    for _ in range(steps):
+        opt.zero_grad()
+        loss = ((model(xt).double() - tt) ** 2).sum()
+        loss.backward()
+        opt.step()
+        got.append(float(loss.detach()))
+    got = np.array(got)
+    dev = np.abs(got - ref) / ref
+    print("C5 fit: loss %.4g -> %.4g (oracle %.4g -> %.4g), max relative deviation %.4f at step %d"
+          % (got[0], got[-1], ref[0], ref[-1], dev.max(), int(dev.argmax())))
+    assert np.all(np.isfinite(got))
+    assert abs(got[0] - ref[0]) <= 1e-3 * ref[0]
+    assert dev.max() <= 0.01
+    assert got[-1] < 0.45 * got[0]
