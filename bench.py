@@ -122,6 +122,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="skip reporting the autotuner's choice")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16X2 comparison leg")
     ap.add_argument("--gen-device", default="cuda", help="where the QR of the workload generator runs")
+    ap.add_argument("--cpu-eigh", type=int, default=1, help="time the oracle's diagonalization (numpy eigh + "
+                    "V_occ V_occ^T) on the host at the headline size as part of cpu_baseline (0: skip)")
     ap.add_argument("--workload", default="density", choices=["density", "batched", "net", "fermi", "md", "sweep"],
                     help="density: the N=8192 headline (default); batched: 64 Hamiltonians of uneven "
                          "sizes in one graph; net: the 20-layer differentiable network at N=2048; fermi: "
@@ -343,6 +345,17 @@ def main():
         }
         log("cpu oracle: %.3f TFLOP/s on %d threads (%.1f s)" % (cpu_rate, cores, tcpu))
         d_ref = odm.dm_construct(w.q, w.eps, w.n_occ)
+        if args.cpu_eigh:
+            # the other host baseline: time-to-D by diagonalization (LAPACK eigh, FP64, all
+            # threads) on the same H, and its distance to the constructed projector
+            tc = time.perf_counter()
+            d_eigh = odm.dm_eigh(w.h, w.n_occ)
+            te = time.perf_counter() - tc
+            out["cpu_baseline"]["eigh_time_to_d_s"] = round(te, 2)
+            out["cpu_baseline"]["eigh_fro_error"] = float(np.linalg.norm(d_eigh - d_ref))
+            out["cpu_baseline"]["eigh_speedup_of_gpu_mixed"] = round(te * 1e3 / ms_per_step, 1)
+            log("cpu eigh: time-to-D %.1f s (%.0fx the GPU mixed-precision call)" % (te, te * 1e3 / ms_per_step))
+            del d_eigh
         acc = {"fro_error": float(np.linalg.norm(d.cpu().numpy() - d_ref)),
                "fro_bound": 1e-3 * math.sqrt(n), "trace_error": abs(info["trace"] - w.n_occ)}
         if d64 is not None:
