@@ -74,20 +74,24 @@ struct Plan {
 };
 
 // The persistent (whole rounds + split tail) schedule needs a tile of 128 or 256 in a
-// split mode; kernel 1 asks for the one-workgroup-per-tile schedule.  The automatic
-// choice takes the persistent schedule for 256 tiles only: with 128 tiles two one-tile
-// workgroups per CU measured faster.
-bool sk_wanted(bool split, int tile, int kernel) {
+// split mode; kernel 1 asks for the one-workgroup-per-tile schedule.  The automatic choice
+// (one layer, split included, MI355X): 128 tiles persistent from n_p = 3072 (n = 3072:
+// 0.156 vs 0.167 ms per tile; 4096: 0.289-0.302 vs 0.339-0.347 ms), one workgroup per tile
+// below; 256 tiles one workgroup per tile below n_p = 6144 (n = 5120: 0.486 vs 0.594 ms
+// persistent) and persistent from there (6144: 0.807 vs 0.937 ms).
+bool sk_wanted(bool split, int tile, int kernel, int np) {
     if (!split || tile < 128 || kernel == 1 || kernel == 8) return false;
-    return kernel != 0 || tile == 256;
+    if (kernel != 0) return true;
+    return tile == 128 ? np >= 3072 : np >= 6144;
 }
 
 // Persistent variant used when the caller leaves the choice open (index into the
 // per-tile variant table of the kernel), the fastest measured on MI355X: for 256 tiles
 // 8 waves with 32-half slices and the rolling fragment pipeline (one layer, split
 // included, at n = 8192: 1.69 ms against 1.74 ms with two fragment sets; n = 16384: 10.49
-// against 11.02 ms); for 128 tiles the 64-half slices.
-int sk_auto_variant(int tile) { return tile == 256 ? 5 : 1; }
+// against 11.02 ms); for 128 tiles the 64-half slices with the rolling pipeline (n = 4096:
+// 0.289 ms against 0.379 ms with two fragment sets).
+int sk_auto_variant(int tile) { return tile == 256 ? 5 : 4; }
 
 // Resolves the squaring schedule for this device; false = one workgroup per tile.
 bool sk_resolve(const Plan& p, StreamK* sk, int* variant) {
@@ -142,11 +146,11 @@ StreamK f64_sk_resolve(int np, void* partial, int* counter) {
 bool f64_sk_space(int np) { return ntiles_upper(np / 128) >= 64; }
 
 int auto_tile_main(int n, bool split) {
-    // split modes: 256 tiles from n = 4096 (136 tiles; measured 690 vs 624 TFLOP/s for
-    // 128 tiles there), persistent once there is a 256 tile per CU (n >= 6144); 128 tiles
-    // from 2048 to 4096; 64 tiles below 2048, where 128 tiles leave CUs idle (one layer at
-    // n = 1024: 0.034 vs 0.049 ms, n = 1536: 0.048 vs 0.064 ms; equal at 2048)
-    if (split) return n < 2048 ? 64 : (n < 4096 ? 128 : 256);
+    // split modes: 128 tiles from 2048 to 4608 (at 4096 the persistent 128-tile schedule
+    // beats every 256-tile one: 0.289-0.302 against 0.307-0.338 ms per layer), 256 tiles
+    // above; 64 tiles below 2048, where 128 tiles leave CUs idle (one layer at n = 1024:
+    // 0.034 vs 0.049 ms, n = 1536: 0.048 vs 0.064 ms; equal at 2048)
+    if (split) return n < 2048 ? 64 : (n <= 4608 ? 128 : 256);
     return n <= 512 ? 64 : 128;
 }
 
@@ -201,7 +205,7 @@ void make_plan(int n, const Opts& o, Plan* p) {
     p->off_y = off;
     off = align_up(off + (o.refine ? 8 * np2 : 0));
     p->kernel = kernel;
-    p->sk_capable = sk_wanted(p->split, p->tile_main, kernel);
+    p->sk_capable = sk_wanted(p->split, p->tile_main, kernel, p->np);
     p->off_sk_partial = off;
     if (p->sk_capable) off = align_up(off + square_sk_partial_bytes(p->tile_main, p->np));
     p->off_sk_counter = off;
@@ -907,7 +911,7 @@ size_t sp2_square_workspace_size(int n, int precision, int tile, int kernel) {
     off = align_up(off + sizeof(double) * 2 * nt);     // partials
     off = align_up(off + sizeof(double) * 2);          // sums
     if (split) off = align_up(off + 4 * (size_t)np * plane_ld(np));
-    if (sk_wanted(split, t, kernel)) {
+    if (sk_wanted(split, t, kernel, np)) {
         off = align_up(off + square_sk_partial_bytes(t, np));
         off = align_up(off + sizeof(int) * kSkCounterInts);
     }
@@ -971,7 +975,7 @@ int sp2_square(const void* dX, void* dY, int n, int precision, int tile, int ker
         pl.np = np;
         pl.tile_main = t;
         pl.kernel = kernel;
-        pl.sk_capable = sk_wanted(true, t, kernel);
+        pl.sk_capable = sk_wanted(true, t, kernel, np);
         StreamK sk;
         memset(&sk, 0, sizeof(sk));
         int variant = 0;
