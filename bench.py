@@ -499,7 +499,8 @@ def bench_batched(args):
 def bench_net(args):
     """The 20-layer network X_{k+1} = W_k X_k^2 + B_k X_k + c_k I at N = 2048 (spectrum
     U[-15,15] eV, mu = 0, kT = 0.2 eV target): one step = forward (split squarings) +
-    backward (checkpoint recomputation + FP32 adjoint) for the loss ||X_20 - T||_F^2."""
+    backward (FP32 adjoint, plus checkpoint recomputation where the library keeps only every
+    c-th layer) for the loss ||X_20 - T||_F^2."""
     import numpy as np
     import torch
 
@@ -543,7 +544,10 @@ def bench_net(args):
         fwd.append(e[0].elapsed_time(e[1]))
         bwd.append(e[1].elapsed_time(e[2]))
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    c = int(math.ceil(math.sqrt(K)))
+    # checkpoint spacing of ckpt_every = 0: every layer kept when the workspace equals that of
+    # c = 1, else ceil(sqrt(K))
+    keep_all = sp2.net_workspace_size(n, K, args.precision, 0) == sp2.net_workspace_size(n, K, args.precision, 1)
+    c = 1 if keep_all else int(math.ceil(math.sqrt(K)))
     recompute = K - (K + c - 1) // c
     f_fwd = K * flop_split_layer(n)
     f_bwd = recompute * flop_split_layer(n) + K * 2 * flop_plain_layer(n)
@@ -555,7 +559,8 @@ def bench_net(args):
         "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f16 forward / f32 adjoint", "data": "synthetic",
         "config": {"workload": "network N=2048, K=20, spectrum U[-15,15] eV, target Fermi-Dirac kT=0.2 eV, "
-                               "checkpoints every %d layers" % c, "precision": args.precision},
+                               + ("every layer kept (no recomputation)" if c == 1 else "checkpoints every %d layers" % c),
+                   "precision": args.precision},
         "forward_ms": round(float(np.mean(fwd)), 3), "backward_ms": round(float(np.mean(bwd)), 3),
         "forward_tflops": round(f_fwd / (np.mean(fwd) * 1e-3) / 1e12, 3),
         "backward_tflops": round(f_bwd / (np.mean(bwd) * 1e-3) / 1e12, 3),

@@ -315,7 +315,8 @@ void sp2_autotune_reset(void);
  *               The FP16X2 planes hold 2^12 X_k, so |X_k| entries must stay below 16.
  *   ckpt_every  c >= 1: X_k is kept for k = 0, c, 2c, ... and the backward recomputes the
  *               layers in between (memory: ceil(K/c) + c + 6 padded matrices); 0 selects
- *               c = ceil(sqrt(K)).
+ *               c = 1 (every layer kept, nothing recomputed) while K + 7 padded FP32
+ *               matrices take at most 8 GiB, else c = ceil(sqrt(K)).
  *   dW, dB, dC  device FP32 arrays of K coefficients.
  *
  * sp2_net_forward writes X_K (n x n FP32, leading dimension ldk) and keeps the checkpoints

@@ -841,6 +841,7 @@ hipError_t launch_dp_t(int tile, int variant, const SquareArgs& a, const SquareA
             case 0: SP2_L(2, 2, 2, 2, 32, 2, 1); break;
             case 1: SP2_L(2, 2, 2, 2, 64, 2, 0); break;
             case 2: SP2_L(2, 2, 2, 2, 16, 4, 0); break;
+            case 3: SP2_L(2, 2, 2, 2, 64, 2, 1); break;
             default: return hipErrorInvalidValue;
         }
     } else {

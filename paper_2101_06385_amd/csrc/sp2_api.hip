@@ -105,10 +105,17 @@ bool sk_resolve(const Plan& p, StreamK* sk, int* variant) {
 }
 
 // Split layer with one workgroup per tile: the direct-to-LDS pipeline for 128/256 tiles
-// (kernel option 0/1), the register-staged kernel for 64 tiles or kernel option 8.
+// (kernel option 0/1), the register-staged kernel for 64 tiles or kernel option 8.  On
+// 128 tiles a single problem takes 64-half slices (one workgroup per CU; one layer at
+// n = 2048: 0.079 against 0.089 ms with 32-half slices and two workgroups per CU, 6144:
+// 0.88 against 0.97 ms); the grouped launches of the batched solve keep the 32-half
+// slices, whose second workgroup per CU hides the prologue and epilogue of the short-K
+// tiles there (114.9 against 116.7 ms per call on the 64-problem batch).
 constexpr int kKernelLegacyTile = 8;
+constexpr int kDpSingle128 = 3;
 hipError_t launch_split_tile_layer(int precision, int tile, int kernel, const SquareArgs& a, hipStream_t s) {
-    if ((tile == 128 || tile == 256) && kernel != kKernelLegacyTile) return launch_square_dp(precision, tile, 0, a, s);
+    if ((tile == 128 || tile == 256) && kernel != kKernelLegacyTile)
+        return launch_square_dp(precision, tile, tile == 128 ? kDpSingle128 : 0, a, s);
     return launch_square_split(precision, tile, a, s);
 }
 

@@ -17,6 +17,10 @@ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 // adjoint variant for n <= 4096 (64 tiles): 0 = 2 LDS stages, two workgroups per CU;
 // 1 = 4 stages, one per CU
 constexpr int kAdjVariantSmall = 0;
+// ckpt_every = 0 keeps every layer (no recomputation in the backward) while the K + 7
+// padded matrices fit in this many bytes, a small share of the device memory; above it
+// the checkpoints are sqrt(K) apart.
+constexpr size_t kKeepAllBytes = size_t(8) << 30;
 
 struct NetPlan {
     int n, np, K, c, nck, precision, tile_main, tile_adj, adj_variant, scale_log2;
@@ -34,9 +38,6 @@ bool net_plan(int n, int K, int precision, int ckpt_every, NetPlan* p) {
     p->precision = precision;
     p->split = precision != SP2_FP32;
     p->scale_log2 = precision == SP2_FP16X2 ? 12 : 0;
-    p->c = ckpt_every ? ckpt_every : (int)ceil(sqrt((double)K));
-    if (p->c > K) p->c = K;
-    p->nck = (K + p->c - 1) / p->c;
     p->tile_main = n <= 256 ? 64 : 128;
     // adjoint: 64 tiles until 128 tiles fill the GPU (136 tiles of 128 at n = 2048 left
     // half the CUs idle)
@@ -50,6 +51,10 @@ bool net_plan(int n, int K, int precision, int ckpt_every, NetPlan* p) {
         square_plain_grid(p->tile_main, p->np, &p->T_main, &p->nt_main, &p->per_main);
     adjoint_grid(p->tile_adj, p->np, &p->T_adj, &p->nt_adj, &p->per_adj);
     const size_t m2 = (size_t)p->np * p->np * sizeof(float);
+    if (ckpt_every) p->c = ckpt_every;
+    else p->c = (size_t)(K + 7) * m2 <= kKeepAllBytes ? 1 : (int)ceil(sqrt((double)K));
+    if (p->c > K) p->c = K;
+    p->nck = (K + p->c - 1) / p->c;
     size_t off = 0;
     p->off_coef = off;
     off = align_up(off + sizeof(float) * 3 * K);
@@ -136,7 +141,8 @@ hipError_t layer(const NetPlan& p, const NetBuffers& b, int k, const float* x_in
     a.per = p.per_main;
     a.out_scale = ldexpf(1.f, -2 * p.scale_log2);
     a.in_scale = ldexpf(1.f, p.scale_log2);
-    if (p.split && p.tile_main == 128) return launch_square_dp(p.precision, 128, 0, a, s);
+    // one workgroup per 128 tile with 64-half K-slices (the single-problem choice)
+    if (p.split && p.tile_main == 128) return launch_square_dp(p.precision, 128, 3, a, s);
     return p.split ? launch_square_split(p.precision, p.tile_main, a, s)
                    : launch_square_plain(p.precision, p.tile_main, a, s);
 }

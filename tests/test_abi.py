@@ -229,3 +229,17 @@ def test_static_entry_point_host_checks():
     assert L.sp2_density_static(None, 10, fake, 10, 10, 5, 0.0, ctypes.byref(o), None, None) == sp2.SP2_EINVAL
     bad = sp2.options(max_layers=500)
     assert L.sp2_density_static(fake, 10, fake, 10, 10, 5, 0.0, ctypes.byref(bad), None, None) == sp2.SP2_EINVAL
+
+
+def test_net_checkpoint_default_keeps_every_layer_while_small():
+    # ckpt_every = 0: every layer kept (K + 7 matrices) while that takes at most 8 GiB,
+    # else checkpoints ceil(sqrt(K)) apart (ceil(K / c) + c + 6 matrices)
+    f16 = sp2.FP16X2
+    L = sp2.lib()
+    for n, K in ((2048, 20), (200, 9)):
+        assert L.sp2_net_workspace_size(n, K, f16, 0) == L.sp2_net_workspace_size(n, K, f16, 1)
+        assert L.sp2_net_workspace_size(n, K, f16, 0) > L.sp2_net_workspace_size(n, K, f16, 5)
+    m2 = 16384 * 16384 * 4
+    assert (20 + 7) * m2 > 8 << 30
+    assert L.sp2_net_workspace_size(16384, 20, f16, 0) == L.sp2_net_workspace_size(16384, 20, f16, 5)
+    assert L.sp2_net_workspace_size(16384, 20, f16, 0) < 20 * m2
