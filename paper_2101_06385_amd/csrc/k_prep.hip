@@ -716,6 +716,20 @@ __global__ __launch_bounds__(kThreads) void k_finalize_g(const BatchProblem* __r
     finalize_body(q.st, q.dstats, q.dstats_blocks, q.init_parts, q.init_tiles);
 }
 
+// Device state of problem blockIdx.x between its region and slot blockIdx.x of a
+// contiguous staging array (to_regions: staging -> region), so that a batched call moves
+// all the states with one host transfer each way.
+static_assert(sizeof(DevState) % 4 == 0, "states move as 32-bit words");
+__global__ __launch_bounds__(64) void k_state_copy_g(const BatchProblem* __restrict__ pr, DevState* stage,
+                                                     int to_regions) {
+    unsigned* r = (unsigned*)pr[blockIdx.x].st;
+    unsigned* g = (unsigned*)(stage + blockIdx.x);
+    for (int i = threadIdx.x; i < (int)(sizeof(DevState) / 4); i += 64) {
+        if (to_regions) r[i] = g[i];
+        else g[i] = r[i];
+    }
+}
+
 inline int grid_for(size_t total) {
     size_t g = (total + kThreads - 1) / kThreads;
     if (g > 8192) g = 8192;
@@ -941,6 +955,10 @@ hipError_t launch_batch_dstats(const BatchProblem* pr, const int* offs, int npro
 }
 hipError_t launch_batch_finalize(const BatchProblem* pr, int nprob, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize_g, dim3(nprob), dim3(kThreads), 0, s, pr);
+    return hipGetLastError();
+}
+hipError_t launch_batch_states(const BatchProblem* pr, DevState* stage, int nprob, int to_regions, hipStream_t s) {
+    hipLaunchKernelGGL(k_state_copy_g, dim3(nprob), dim3(64), 0, s, pr, stage, to_regions);
     return hipGetLastError();
 }
 }  // namespace sp2

@@ -1031,15 +1031,20 @@ struct BatchLayout {
     std::vector<int> nontrivial;        // indices of problems that run the recursion
     std::vector<Plan> plans;
     std::vector<size_t> region;         // byte offset of each problem's region
-    size_t off_probs, off_sq, off_offs, off_map, total;
+    size_t off_probs, off_sq, off_offs, off_map, off_stage, total;
     int n_offs;                         // stride of the offset arrays (batch + 1)
     size_t map_ints;                    // capacity of the tile map of the 128-tile grouped launches
 };
 
 // Tile map of the grouped 128-tile launches (squaring and FP64 refinement): every tile of
-// the problems `order` lists, each problem's tiles on one XCD (so they share its L2),
-// problems taken largest first and given to the XCD with the least work so far (work ~ n_p^3).
-// Returns per (map entries per XCD); map has 8 per entries.
+// the problems `order` lists.  Each problem's tiles are cut into kMapParts contiguous runs
+// of the strip order, each run on one XCD (so that the tiles of a run share its L2);
+// problems go largest first, and each run to the XCD with the least work so far (a run's
+// work ~ its tiles x n_p).  Four runs per problem: the 64-problem batch (N = 256..3008)
+// takes 107.3 ms per call, against 111.7 ms with whole problems per XCD (the last layers,
+// with few problems left, then kept only some XCDs busy), 109.2 ms with 2 runs and
+// 109.0 ms with 8 (each XCD's L2 then holds panels of every problem).
+constexpr int kMapParts = 4;
 int build_tile_map(const std::vector<Plan>& plans, const std::vector<int>& problems, std::vector<int>* map) {
     std::vector<int> order(problems.size());
     for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
@@ -1050,11 +1055,18 @@ int build_tile_map(const std::vector<Plan>& plans, const std::vector<int>& probl
     double load[8] = {};
     for (int k : order) {
         const Plan& p = plans[problems[k]];
-        int x = 0;
-        for (int j = 1; j < 8; ++j)
-            if (load[j] < load[x]) x = j;
-        for (int t = 0; t < p.main_tiles; ++t) bins[x].push_back((k << kTileMapShift) | t);
-        load[x] += (double)p.np * p.np * p.np;
+        const int nt = p.main_tiles;
+        const int parts = nt < kMapParts ? nt : kMapParts;
+        bool used[8] = {};
+        for (int r = 0; r < parts; ++r) {
+            const int t0 = (int)((long long)nt * r / parts), t1 = (int)((long long)nt * (r + 1) / parts);
+            int x = -1;
+            for (int j = 0; j < 8; ++j)
+                if (!used[j] && (x < 0 || load[j] < load[x])) x = j;
+            used[x] = true;
+            for (int t = t0; t < t1; ++t) bins[x].push_back((k << kTileMapShift) | t);
+            load[x] += (double)(t1 - t0) * p.np;
+        }
     }
     size_t per = 0;
     for (auto& b : bins) per = b.size() > per ? b.size() : per;
@@ -1102,6 +1114,8 @@ bool batch_layout(int batch, const int* n, const int* n_occ, const Opts& o, Batc
         for (int i = 0; i < batch; ++i) L->map_ints += 8 * (size_t)L->plans[i].main_tiles;
     L->off_map = off;
     off = align_up(off + sizeof(int) * L->map_ints);
+    L->off_stage = off;   // the device states of the problems, staged for one transfer
+    off = align_up(off + sizeof(DevState) * batch);
     // then one single-problem region per problem; its DevState sits at the region's start
     for (int i = 0; i < batch; ++i) {
         L->region[i] = off;
@@ -1134,6 +1148,54 @@ size_t sp2_batched_workspace_size(int batch, const int* n, const sp2_options* op
 }
 
 }  // extern "C"
+
+namespace {
+
+// Instantiated graphs of batched calls, keyed by everything the captured launches depend
+// on (device, workspace address, layout and launch sizes); the most recent kGraphCache.
+// Kept until the process ends.
+constexpr size_t kGraphCache = 16;
+struct GraphEntry {
+    std::vector<long long> key;
+    hipGraphExec_t exec;
+};
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;   // least recently used first
+hipGraphExec_t graph_cache_find(const std::vector<long long>& key) {
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    for (size_t i = 0; i < g_graphs.size(); ++i)
+        if (g_graphs[i].key == key) {
+            GraphEntry e = g_graphs[i];
+            g_graphs.erase(g_graphs.begin() + i);
+            g_graphs.push_back(e);
+            return e.exec;
+        }
+    return nullptr;
+}
+void graph_cache_add(const std::vector<long long>& key, hipGraphExec_t exec) {
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    if (g_graphs.size() >= kGraphCache) {
+        (void)hipGraphExecDestroy(g_graphs.front().exec);
+        g_graphs.erase(g_graphs.begin());
+    }
+    g_graphs.push_back({key, exec});
+}
+// One non-blocking stream per device for the batched sequence, created on first use.
+hipStream_t batch_stream() {
+    static std::mutex mu;
+    static std::vector<std::pair<int, hipStream_t>> streams;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    for (auto& p : streams)
+        if (p.first == dev) return p.second;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    streams.push_back({dev, s});
+    return s;
+}
+
+}  // namespace
 
 // The batched driver; homo/lumo (host, one per problem, or null) select accelerated layers.
 static int run_batched(int batch, const double* const* dH, const int* ldh, double* const* dD, const int* ldd,
@@ -1271,8 +1333,8 @@ static int run_batched(int batch, const double* const* dH, const int* ldh, doubl
         }
         const int* d_map = (const int*)(ws + L.off_map);
         SP2_TRY(hipMemcpy(ws + L.off_offs, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice));
-        for (int k = 0; k < nt; ++k)
-            SP2_TRY(hipMemcpy(ws + L.region[L.nontrivial[k]], &states[k], sizeof(DevState), hipMemcpyHostToDevice));
+        DevState* d_stage = (DevState*)(ws + L.off_stage);
+        SP2_TRY(hipMemcpy(d_stage, states.data(), sizeof(DevState) * nt, hipMemcpyHostToDevice));
         const SquareArgs* d_sq = (const SquareArgs*)(ws + L.off_sq);
         const int* d_offs = (const int*)(ws + L.off_offs);
         const int* d_og = d_offs;
@@ -1282,9 +1344,10 @@ static int run_batched(int batch, const double* const* dH, const int* ldh, doubl
         const int* d_od = d_or + L.n_offs;
 
         // ---------------------------------------------------------------- the sequence
-        hipStream_t cs = nullptr;
-        SP2_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipStream_t cs = batch_stream();
+        if (!cs) return SP2_EDEVICE;
         auto enqueue = [&](hipStream_t s) -> int {
+            SP2_TRY(launch_batch_states(d_probs, d_stage, nt, 1, s));
             SP2_TRY(launch_batch_gershgorin(d_probs, d_og, nt, o_g[nt], s));
             SP2_TRY(launch_batch_bounds(d_probs, nt, s));
             SP2_TRY(launch_batch_init(o.precision, d_probs, d_oi, nt, o_i[nt], s));
@@ -1304,35 +1367,54 @@ static int run_batched(int batch, const double* const* dH, const int* ldh, doubl
                                       : launch_square_plain_g(SP2_FP64, L.tile, d_sq + step * nt, d_or, nt, o_r[nt], s));
             SP2_TRY(launch_batch_dstats(d_probs, d_od, nt, o_d[nt], s));
             SP2_TRY(launch_batch_finalize(d_probs, nt, s));
+            SP2_TRY(launch_batch_states(d_probs, d_stage, nt, 0, s));
             return SP2_OK;
         };
         int rc = SP2_OK;
         if (use_graph) {
-            hipGraph_t graph = nullptr;
-            hipGraphExec_t exec = nullptr;
-            if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = SP2_EDEVICE;
-            if (rc == SP2_OK) {
-                rc = enqueue(cs);
-                const hipError_t e = hipStreamEndCapture(cs, &graph);
-                if (rc == SP2_OK && e != hipSuccess) rc = SP2_EDEVICE;
+            // The graph depends only on the addresses and launch sizes below (the problems'
+            // matrices, coefficients and states are read from the descriptors uploaded
+            // above), so a call with the same layout in the same workspace reuses it.
+            int dev = 0;
+            SP2_TRY(hipGetDevice(&dev));
+            const std::vector<long long> key = {dev, (long long)(uintptr_t)ws, (long long)L.total, L.batch, nt,
+                                                L.tile, o.precision, o.max_layers, map_per, o_g[nt], o_i[nt],
+                                                o_m[nt], o_r[nt], o_d[nt], (long long)L.off_probs,
+                                                (long long)L.off_sq, (long long)L.off_offs, (long long)L.off_map,
+                                                (long long)L.off_stage};
+            hipGraphExec_t exec = graph_cache_find(key);
+            if (!exec) {
+                hipGraph_t graph = nullptr;
+                if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = SP2_EDEVICE;
+                if (rc == SP2_OK) {
+                    rc = enqueue(cs);
+                    const hipError_t e = hipStreamEndCapture(cs, &graph);
+                    if (rc == SP2_OK && e != hipSuccess) rc = SP2_EDEVICE;
+                }
+                if (rc == SP2_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                    exec = nullptr;
+                    rc = SP2_EDEVICE;
+                }
+                if (graph) (void)hipGraphDestroy(graph);
+                if (exec) graph_cache_add(key, exec);
             }
-            if (rc == SP2_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) rc = SP2_EDEVICE;
             if (rc == SP2_OK && hipGraphLaunch(exec, cs) != hipSuccess) rc = SP2_EDEVICE;
             if (hipStreamSynchronize(cs) != hipSuccess && rc == SP2_OK) rc = SP2_EDEVICE;
-            if (exec) (void)hipGraphExecDestroy(exec);
-            if (graph) (void)hipGraphDestroy(graph);
         } else {
             rc = enqueue(cs);
             if (hipStreamSynchronize(cs) != hipSuccess && rc == SP2_OK) rc = SP2_EDEVICE;
         }
-        (void)hipStreamDestroy(cs);
         if (rc != SP2_OK) return rc;
     }
     SP2_TRY(hipStreamSynchronize(user));
+    std::vector<DevState> done(nt);
+    if (nt > 0)
+        SP2_TRY(hipMemcpy(done.data(), ws + L.off_stage, sizeof(DevState) * nt, hipMemcpyDeviceToHost));
     int worst = SP2_OK;
-    for (int i = 0; i < batch; ++i) {
+    for (int i = 0, k = 0; i < batch; ++i) {
         DevState host;
-        SP2_TRY(hipMemcpy(&host, ws + L.region[i], sizeof(DevState), hipMemcpyDeviceToHost));
+        if (k < nt && L.nontrivial[k] == i) host = done[k++];
+        else SP2_TRY(hipMemcpy(&host, ws + L.region[i], sizeof(DevState), hipMemcpyDeviceToHost));
         if (infos) fill_info(host, &L.plans[i], &infos[i]);
         if (host.status != SP2_OK && worst == SP2_OK) worst = host.status;
     }

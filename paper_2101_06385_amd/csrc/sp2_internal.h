@@ -180,6 +180,7 @@ hipError_t launch_batch_control(const BatchProblem* pr, int nprob, int layer, hi
 hipError_t launch_batch_select(const BatchProblem* pr, int nprob, int per_problem, hipStream_t s);
 hipError_t launch_batch_dstats(const BatchProblem* pr, const int* offs, int nprob, int blocks, hipStream_t s);
 hipError_t launch_batch_finalize(const BatchProblem* pr, int nprob, hipStream_t s);
+hipError_t launch_batch_states(const BatchProblem* pr, DevState* stage, int nprob, int to_regions, hipStream_t s);
 
 // Host-side launchers (defined next to their kernels).
 hipError_t launch_square_split(int precision, int tile, const SquareArgs& a, hipStream_t s);
