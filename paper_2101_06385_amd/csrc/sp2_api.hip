@@ -1197,6 +1197,9 @@ hipStream_t batch_stream() {
 
 }  // namespace
 
+// Layers in the first part of a batched sequence (see run_batched).
+constexpr int kBatchLayersA = 48;
+
 // The batched driver; homo/lumo (host, one per problem, or null) select accelerated layers.
 static int run_batched(int batch, const double* const* dH, const int* ldh, double* const* dD, const int* ldd,
                        const int* n, const int* n_occ, const double* homo, const double* lumo, double tol,
@@ -1346,12 +1349,14 @@ static int run_batched(int batch, const double* const* dH, const int* ldh, doubl
         // ---------------------------------------------------------------- the sequence
         hipStream_t cs = batch_stream();
         if (!cs) return SP2_EDEVICE;
-        auto enqueue = [&](hipStream_t s) -> int {
-            SP2_TRY(launch_batch_states(d_probs, d_stage, nt, 1, s));
-            SP2_TRY(launch_batch_gershgorin(d_probs, d_og, nt, o_g[nt], s));
-            SP2_TRY(launch_batch_bounds(d_probs, nt, s));
-            SP2_TRY(launch_batch_init(o.precision, d_probs, d_oi, nt, o_i[nt], s));
-            for (int layer = 1; layer <= o.max_layers + 1; ++layer) {
+        // The sequence runs in three parts: A = set-up and layers 1 .. la, B = layers
+        // la + 1 .. max_layers (and the final check), C = refinement and statistics.  B is
+        // skipped when every problem has stopped within A (the host reads the states
+        // between A and B), so the launches of layers after the last problem stopped are
+        // not made at all; la covers the layer counts of typical batches.
+        const int la = o.max_layers < kBatchLayersA ? o.max_layers : kBatchLayersA;
+        auto layers = [&](hipStream_t s, int l0, int l1) -> int {
+            for (int layer = l0; layer <= l1; ++layer) {
                 SP2_TRY(launch_batch_control(d_probs, nt, layer, s));
                 if (layer > o.max_layers) break;
                 const SquareArgs* a = d_sq + ((layer - 1) & 1) * nt;
@@ -1361,49 +1366,72 @@ static int run_batched(int batch, const double* const* dH, const int* ldh, doubl
                     SP2_TRY(L.tile == 128 ? launch_square_dp_g(o.precision, 128, 0, a, d_map, map_per, s)
                                           : launch_square_split_g(o.precision, L.tile, a, d_om, nt, o_m[nt], s));
             }
-            SP2_TRY(launch_batch_select(d_probs, nt, 64, s));
-            for (int step = 2; step <= 3; ++step)
-                SP2_TRY(L.tile == 128 ? launch_square_f64_g(d_sq + step * nt, d_map, map_per, s)
-                                      : launch_square_plain_g(SP2_FP64, L.tile, d_sq + step * nt, d_or, nt, o_r[nt], s));
-            SP2_TRY(launch_batch_dstats(d_probs, d_od, nt, o_d[nt], s));
-            SP2_TRY(launch_batch_finalize(d_probs, nt, s));
-            SP2_TRY(launch_batch_states(d_probs, d_stage, nt, 0, s));
             return SP2_OK;
         };
-        int rc = SP2_OK;
-        if (use_graph) {
-            // The graph depends only on the addresses and launch sizes below (the problems'
-            // matrices, coefficients and states are read from the descriptors uploaded
-            // above), so a call with the same layout in the same workspace reuses it.
-            int dev = 0;
-            SP2_TRY(hipGetDevice(&dev));
-            const std::vector<long long> key = {dev, (long long)(uintptr_t)ws, (long long)L.total, L.batch, nt,
-                                                L.tile, o.precision, o.max_layers, map_per, o_g[nt], o_i[nt],
-                                                o_m[nt], o_r[nt], o_d[nt], (long long)L.off_probs,
+        auto part = [&](hipStream_t s, int which) -> int {
+            if (which == 0) {
+                SP2_TRY(launch_batch_states(d_probs, d_stage, nt, 1, s));
+                SP2_TRY(launch_batch_gershgorin(d_probs, d_og, nt, o_g[nt], s));
+                SP2_TRY(launch_batch_bounds(d_probs, nt, s));
+                SP2_TRY(launch_batch_init(o.precision, d_probs, d_oi, nt, o_i[nt], s));
+                SP2_TRY(layers(s, 1, la < o.max_layers ? la : o.max_layers + 1));
+                SP2_TRY(launch_batch_states(d_probs, d_stage, nt, 0, s));   // for the check after A
+            } else if (which == 1) {
+                SP2_TRY(layers(s, la + 1, o.max_layers + 1));
+            } else {
+                SP2_TRY(launch_batch_select(d_probs, nt, 64, s));
+                for (int step = 2; step <= 3; ++step)
+                    SP2_TRY(L.tile == 128
+                                ? launch_square_f64_g(d_sq + step * nt, d_map, map_per, s)
+                                : launch_square_plain_g(SP2_FP64, L.tile, d_sq + step * nt, d_or, nt, o_r[nt], s));
+                SP2_TRY(launch_batch_dstats(d_probs, d_od, nt, o_d[nt], s));
+                SP2_TRY(launch_batch_finalize(d_probs, nt, s));
+                SP2_TRY(launch_batch_states(d_probs, d_stage, nt, 0, s));
+            }
+            return SP2_OK;
+        };
+        int dev = 0;
+        SP2_TRY(hipGetDevice(&dev));
+        // The graphs depend only on the addresses and launch sizes below (the problems'
+        // matrices, coefficients and states are read from the descriptors uploaded above),
+        // so a call with the same layout in the same workspace reuses them.
+        auto run_part = [&](int which) -> int {
+            if (!use_graph) return part(cs, which);
+            const std::vector<long long> key = {which, dev, (long long)(uintptr_t)ws, (long long)L.total, L.batch,
+                                                nt, L.tile, o.precision, o.max_layers, la, map_per, o_g[nt],
+                                                o_i[nt], o_m[nt], o_r[nt], o_d[nt], (long long)L.off_probs,
                                                 (long long)L.off_sq, (long long)L.off_offs, (long long)L.off_map,
                                                 (long long)L.off_stage};
             hipGraphExec_t exec = graph_cache_find(key);
             if (!exec) {
+                int prc = SP2_OK;
                 hipGraph_t graph = nullptr;
-                if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = SP2_EDEVICE;
-                if (rc == SP2_OK) {
-                    rc = enqueue(cs);
-                    const hipError_t e = hipStreamEndCapture(cs, &graph);
-                    if (rc == SP2_OK && e != hipSuccess) rc = SP2_EDEVICE;
-                }
-                if (rc == SP2_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return SP2_EDEVICE;
+                prc = part(cs, which);
+                const hipError_t e = hipStreamEndCapture(cs, &graph);
+                if (prc == SP2_OK && e != hipSuccess) prc = SP2_EDEVICE;
+                if (prc == SP2_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
                     exec = nullptr;
-                    rc = SP2_EDEVICE;
+                    prc = SP2_EDEVICE;
                 }
                 if (graph) (void)hipGraphDestroy(graph);
-                if (exec) graph_cache_add(key, exec);
+                if (prc != SP2_OK) return prc;
+                graph_cache_add(key, exec);
             }
-            if (rc == SP2_OK && hipGraphLaunch(exec, cs) != hipSuccess) rc = SP2_EDEVICE;
-            if (hipStreamSynchronize(cs) != hipSuccess && rc == SP2_OK) rc = SP2_EDEVICE;
-        } else {
-            rc = enqueue(cs);
-            if (hipStreamSynchronize(cs) != hipSuccess && rc == SP2_OK) rc = SP2_EDEVICE;
+            return hipGraphLaunch(exec, cs) == hipSuccess ? SP2_OK : SP2_EDEVICE;
+        };
+        int rc = run_part(0);
+        if (rc == SP2_OK && la < o.max_layers) {
+            std::vector<DevState> mid(nt);
+            if (hipStreamSynchronize(cs) != hipSuccess ||
+                hipMemcpy(mid.data(), d_stage, sizeof(DevState) * nt, hipMemcpyDeviceToHost) != hipSuccess)
+                rc = SP2_EDEVICE;
+            bool all_stopped = true;
+            for (int k = 0; k < nt && rc == SP2_OK; ++k) all_stopped = all_stopped && mid[k].stopped;
+            if (rc == SP2_OK && !all_stopped) rc = run_part(1);
         }
+        if (rc == SP2_OK) rc = run_part(2);
+        if (hipStreamSynchronize(cs) != hipSuccess && rc == SP2_OK) rc = SP2_EDEVICE;
         if (rc != SP2_OK) return rc;
     }
     SP2_TRY(hipStreamSynchronize(user));

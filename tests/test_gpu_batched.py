@@ -134,3 +134,25 @@ def test_batched_config4_full_vs_oracle():
     assert len(outs) == 64
     for w, d, info in zip(ws, outs, infos):
         _check_vs_oracle(w, d, info)
+
+
+@pytest.mark.parametrize("max_layers", [30, 100])
+def test_batched_layers_beyond_the_first_graph_part(max_layers):
+    """The batched sequence runs layers 1..48 first and the rest only if a problem is still
+    running: a problem with a 2e-4 eV gap needs more than 48 layers, the others stop
+    earlier; with a cap of 30 the cap falls in the first part.  Each result must equal
+    the single path's."""
+    ws = [wl.gapped(70, 200, 90, homo=-1e-4, lumo=1e-4), wl.gapped(71, 130, 40), wl.gapped(72, 300, 150)]
+    hs = [torch.from_numpy(w.h).to(DEV) for w in ws]
+    for graph in (True, False):
+        outs, infos = sp2.density_batched(hs, [w.n_occ for w in ws], tile=64, max_layers=max_layers,
+                                          use_graph=graph)
+        for w, h, d, info in zip(ws, hs, outs, infos):
+            d1, i1 = sp2.density(h, w.n_occ, tile=64, kernel=1, max_layers=max_layers)
+            assert info["layers"] == i1["layers"] and info["sigma"] == i1["sigma"], w.name
+            assert info["status"] == i1["status"], w.name
+            assert torch.equal(d, d1), w.name
+        if max_layers == 100:
+            assert infos[0]["layers"] > 48 and max(i["layers"] for i in infos[1:]) <= 48
+        else:
+            assert infos[0]["layers"] >= 29
