@@ -462,11 +462,14 @@ def bench_batched(args):
         sp2.density_batched(hs, occ, precision=args.precision, outs=souts, workspace=wsbuf, gaps=gaps)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
+        each = []
         for _ in range(args.steps):
+            tc = time.perf_counter()
             _, ainfos = sp2.density_batched(hs, occ, precision=args.precision, outs=souts, workspace=wsbuf, gaps=gaps)
+            each.append(round((time.perf_counter() - tc) * 1e3, 2))
         torch.cuda.synchronize()
         ams = (time.perf_counter() - t3) * 1e3 / args.steps
-        out["accelerated"] = {"ms_per_call": round(ams, 3), "speedup_vs_plain": round(ms / ams, 3),
+        out["accelerated"] = {"ms_per_call": round(ams, 3), "ms_each_call": each, "speedup_vs_plain": round(ms / ams, 3),
                               "layers": {"min": min(i["layers"] for i in ainfos),
                                          "max": max(i["layers"] for i in ainfos)},
                               "status": sorted(set(i["status_name"] for i in ainfos))}
