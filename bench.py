@@ -202,7 +202,7 @@ def main():
                                                               info["status_name"], value))
 
     out = {
-        "metric": METRIC,
+        "metric": METRIC if n == 8192 else METRIC.replace("N=8192", "N=%d" % n),
         "value": round(value, 3),
         "unit": "TFLOP/s",
         "n_gpus": 1,
