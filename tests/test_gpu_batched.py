@@ -156,3 +156,22 @@ def test_batched_layers_beyond_the_first_graph_part(max_layers):
             assert infos[0]["layers"] > 48 and max(i["layers"] for i in infos[1:]) <= 48
         else:
             assert infos[0]["layers"] >= 29
+
+
+def test_batched_cached_graphs_follow_the_layout():
+    """Instantiated graphs are reused per (workspace, layout): alternating two batches of
+    different sizes in one workspace, and then new matrices of the first batch's sizes,
+    must give each call exactly what a fresh single call gives."""
+    # sizes above 512, where the single path also refines on 128 tiles
+    a = [wl.gapped(80 + i, n, n // 3) for i, n in enumerate((530, 600, 650))]
+    b = [wl.gapped(90 + i, n, n // 2) for i, n in enumerate((520, 700))]
+    c = [wl.gapped(95 + i, n, n // 4) for i, n in enumerate((530, 600, 650))]
+    o = sp2.options("fp16x2", tile=128)
+    ws = sp2.alloc_workspace(max(sp2.batched_workspace_size([w.n for w in s], o) for s in (a, b)), DEV)
+    for batch in (a, b, a, c, b):
+        hs = [torch.from_numpy(w.h).to(DEV) for w in batch]
+        outs, infos = sp2.density_batched(hs, [w.n_occ for w in batch], tile=128, workspace=ws)
+        for w, h, d, info in zip(batch, hs, outs, infos):
+            d1, i1 = sp2.density(h, w.n_occ, tile=128, kernel=1)
+            assert info["layers"] == i1["layers"], w.name
+            assert torch.equal(d, d1), w.name
